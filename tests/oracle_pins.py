@@ -1,0 +1,236 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` takes an ``oracle.Oracle`` and raises AssertionError when the
+oracle disagrees with something other than itself:
+
+* the Sylvester Hadamard matrix, built two independent ways (scipy's
+  ``hadamard`` and Kronecker powers of [[1, 1], [1, -1]]), which in natural
+  order is the matrix of Eq. 2 (section 2);
+* closed forms: e_0 -> all ones, a constant c -> c 2^n delta_0, the Walsh
+  function chi_s -> 2^n delta_s, the planted peak W(s) = 2^n - 2 #errors;
+* identities: the involution H(Hx) = 2^n x, Parseval sum W^2 = 2^n sum x^2,
+  linearity, and reduction mod 2^32 of an exact 64-bit result;
+* the three algorithms of the paper (Fig. 1, Fig. 2, Fig. 3), which must
+  agree bit for bit on integers;
+* the threshold pass of the problem statement (strict |y_k| > T, ascending
+  k, true count beyond the capacity);
+* the orthonormal scale 2^(-n/2) and the gradient of a weighted square loss,
+  checked by central finite differences (exact for a quadratic up to
+  rounding).
+
+The mutation test runs every pin against builds of the oracle with a planted
+mistake and requires each such build to fail at least one pin.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+import synth
+
+
+def _sylvester_kron(n: int) -> np.ndarray:
+    H = np.ones((1, 1), dtype=np.int64)
+    H2 = np.array([[1, 1], [1, -1]], dtype=np.int64)
+    for _ in range(n):
+        H = np.kron(H2, H)
+    return H
+
+
+def pin_def_vs_sylvester(O):
+    for n in range(0, 10):
+        x = synth.ints(1 << n, 100 + n, -1000, 1000)
+        H = scipy.linalg.hadamard(1 << n).astype(np.int64)
+        assert np.array_equal(O.wht_def(x), H @ x), n
+        assert np.array_equal(_sylvester_kron(n) @ x, H @ x), n
+        xf = synth.normal(1 << n, 200 + n).astype(np.float64)
+        assert np.allclose(O.wht_def(xf), H.astype(np.float64) @ xf, rtol=0, atol=1e-9), n
+
+
+def pin_def_at_vs_sylvester(O):
+    for n in (3, 7, 10):
+        H = scipy.linalg.hadamard(1 << n).astype(np.int64)
+        x32 = synth.ints(1 << n, 7 + n, -(1 << 20), 1 << 20, dtype=np.int32)
+        x64 = synth.ints(1 << n, 9 + n, -(1 << 40), 1 << 40, dtype=np.int64)
+        ks = [0, 1, (1 << n) - 1, (1 << n) // 3]
+        assert np.array_equal(O.wht_def_at(x32, ks), (H @ x32.astype(np.int64))[ks])
+        assert np.array_equal(O.wht_def_at(x64, ks), (H @ x64)[ks])
+
+
+def pin_fig1_vs_sylvester(O):
+    for n in range(0, 11):
+        H = scipy.linalg.hadamard(1 << n).astype(np.int64)
+        x = synth.ints(1 << n, 300 + n, -1000, 1000)
+        ref = H @ x
+        assert np.array_equal(O.wht_fig1(x.astype(np.int32)), ref.astype(np.int32)), n
+        assert np.array_equal(O.wht_fig1(x), ref), n
+        xf = synth.normal(1 << n, 400 + n)
+        assert np.allclose(O.wht_fig1(xf), H @ xf.astype(np.float64), rtol=0, atol=1e-9), n
+
+
+def pin_fig1_vs_def(O):
+    for n in (11, 12):
+        x = synth.ints(1 << n, 500 + n, -(1 << 20), 1 << 20)
+        assert np.array_equal(O.wht_fig1(x), O.wht_def(x)), n
+
+
+def pin_closed_forms(O):
+    for n in (1, 5, 13, 18):
+        N = 1 << n
+        d = np.zeros(N, dtype=np.int32)
+        d[0] = 1
+        assert np.array_equal(O.wht_fig1(d), np.ones(N, dtype=np.int32)), n
+        c = np.full(N, -3, dtype=np.int64)
+        want = np.zeros(N, dtype=np.int64)
+        want[0] = -3 * N
+        assert np.array_equal(O.wht_fig1(c), want), n
+        # Walsh function chi_s: the planted signal with no noise (p = 0).
+        chi, s, err = synth.planted(n, 11 + n, 0.0, dtype=np.int32)
+        assert err == 0
+        want = np.zeros(N, dtype=np.int32)
+        want[s] = N
+        assert np.array_equal(O.wht_fig1(chi), want), n
+
+
+def pin_closed_forms_def(O):
+    n = 8
+    N = 1 << n
+    d = np.zeros(N, dtype=np.int64)
+    d[0] = 1
+    assert np.array_equal(O.wht_def(d), np.ones(N, dtype=np.int64))
+    chi, s, _ = synth.planted(n, 5, 0.0, dtype=np.int64)
+    want = np.zeros(N, dtype=np.int64)
+    want[s] = N
+    assert np.array_equal(O.wht_def(chi), want)
+    assert O.wht_def_at(chi, [s])[0] == N
+
+
+def pin_involution_parseval(O):
+    for n in (4, 12, 16):
+        N = 1 << n
+        x = synth.ints(N, 600 + n, -100, 100)
+        y = O.wht_fig1(x)
+        assert np.array_equal(O.wht_fig1(y), N * x), n
+        assert int(np.sum(y * y)) == N * int(np.sum(x * x)), n
+
+
+def pin_linearity_and_wrap(O):
+    n = 12
+    N = 1 << n
+    a = synth.ints(N, 1, -(1 << 30), 1 << 30)
+    b = synth.ints(N, 2, -(1 << 30), 1 << 30)
+    wa, wb = O.wht_fig1(a), O.wht_fig1(b)
+    assert np.array_equal(O.wht_fig1(3 * a - 5 * b), 3 * wa - 5 * wb)
+    # int32 results are the exact 64-bit results reduced mod 2^32.
+    a32 = a.astype(np.int32)
+    exact = O.wht_fig1(a32.astype(np.int64))
+    assert np.array_equal(O.wht_fig1(a32), exact.astype(np.int32))
+    assert np.any(np.abs(exact) > (1 << 31))  # the case really wraps
+
+
+def pin_planted_peak(O):
+    for n, p, seed in ((16, 0.45, 2), (20, 0.45, 3), (18, 0.48, 4)):
+        x, s, err = synth.planted(n, seed, p, dtype=np.int32)
+        y = O.wht_fig1(x)
+        assert int(y[s]) == (1 << n) - 2 * err, n
+        assert int(np.argmax(np.abs(y.astype(np.int64)))) == s, n
+        assert int(O.wht_def_at(x, [s])[0]) == (1 << n) - 2 * err, n
+
+
+def pin_fig2_fig3(O):
+    for n, qs in ((3, (0, 1, 2)), (10, (0, 1, 2, 3)), (16, (1, 2, 4))):
+        x32 = synth.signs(1 << n, 20 + n)
+        x64 = synth.ints(1 << n, 30 + n, -(1 << 40), 1 << 40)
+        r32, r64 = O.wht_fig1(x32), O.wht_fig1(x64)
+        for q in qs:
+            assert np.array_equal(O.wht_fig2(x32, q), r32), (n, q)
+            assert np.array_equal(O.wht_fig2(x64, q), r64), (n, q)
+        for B in range(0, n + 1, 3):
+            assert np.array_equal(O.wht_fig3(x64, B), r64), (n, B)
+
+
+def pin_threshold(O):
+    y = np.array([5, -7, 0, 7, -2147483648, 2147483647, 6, -6], dtype=np.int32)
+    idx, val, cnt = O.threshold(y, 6)
+    assert cnt == 4 and list(idx) == [1, 3, 4, 5] and list(val) == [-7, 7, -2147483648, 2147483647]
+    idx, val, cnt = O.threshold(y, 6, cap=2)
+    assert cnt == 4 and list(idx) == [1, 3]
+    idx, val, cnt = O.threshold(y, -1)
+    assert cnt == 8 and list(idx) == list(range(8))
+    idx, val, cnt = O.threshold(y, 2147483647)
+    assert cnt == 1 and list(idx) == [4]
+    y64 = np.array([-(1 << 62), 1 << 40, -(1 << 63), 3], dtype=np.int64)
+    idx, val, cnt = O.threshold(y64, 1 << 40)
+    assert cnt == 2 and list(idx) == [0, 2]
+    yf = np.array([0.5, -1.5, 1.0, -1.0, 2.0], dtype=np.float64)
+    idx, val, cnt = O.threshold(yf, 1.0)
+    assert cnt == 2 and list(idx) == [1, 4] and list(val) == [-1.5, 2.0]
+    # against a numpy scan of a transformed planted signal
+    x, s, _ = synth.planted(14, 9, 0.3)
+    w = O.wht_fig1(x)
+    T = 6 * (1 << 7)
+    idx, val, cnt = O.threshold(w, T)
+    want = np.nonzero(np.abs(w.astype(np.int64)) > T)[0]
+    assert cnt == len(want) and np.array_equal(idx, want) and np.array_equal(val, w[want])
+    assert s in set(idx.tolist())
+
+
+def pin_orthonormal(O):
+    for n in (0, 1, 5, 10):
+        N = 1 << n
+        assert abs(O.orthonormal_scale(n) ** 2 * N - 1.0) < 1e-15
+        x = synth.normal((3, N), 40 + n).astype(np.float64)
+        y = O.wht_batch(x, n, True)
+        assert np.allclose(O.wht_batch(y, n, True), x, rtol=0, atol=1e-12)
+        assert np.allclose((y * y).sum(1), (x * x).sum(1), rtol=1e-13)
+        H = scipy.linalg.hadamard(N).astype(np.float64)
+        assert np.allclose(y, x @ H / np.sqrt(N), rtol=0, atol=1e-12)
+
+
+def pin_ragged(O):
+    lg, off, tot = synth.ragged(9, 0, 7, 3)
+    x = synth.normal(tot, 5)
+    y = O.wht_ragged(x, off, lg, True)
+    for t in range(9):
+        N = 1 << int(lg[t])
+        seg = x[off[t]:off[t] + N].astype(np.float64)
+        H = scipy.linalg.hadamard(N).astype(np.float64)
+        assert np.allclose(y[off[t]:off[t] + N], H @ seg / np.sqrt(N), rtol=0, atol=1e-12)
+
+
+def pin_gradient(O):
+    n, B = 5, 2
+    N = 1 << n
+    x = synth.normal((B, N), 7).astype(np.float64)
+    w = synth.uniform((B, N), 8).astype(np.float64)
+    g = O.grad_weighted_square(x, w, n)
+    H = scipy.linalg.hadamard(N).astype(np.float64) / np.sqrt(N)
+
+    def loss(z):
+        return float(np.sum(w * (z @ H) ** 2))
+
+    eps = 1e-3
+    fd = np.zeros_like(x)
+    for b in range(B):
+        for i in range(N):
+            e = np.zeros_like(x)
+            e[b, i] = eps
+            fd[b, i] = (loss(x + e) - loss(x - e)) / (2 * eps)
+    assert np.allclose(g, fd, rtol=1e-8, atol=1e-8)
+
+
+def pin_norms(O):
+    lg, off, tot = synth.ragged(5, 1, 6, 4)
+    x = synth.normal(tot, 1)
+    y = synth.normal(tot, 2)
+    r = synth.normal(tot, 3).astype(np.float64)
+    sx, sy, se = O.norms(x, y, r, off, lg)
+    for t in range(5):
+        sl = slice(off[t], off[t] + (1 << int(lg[t])))
+        xd, yd = x[sl].astype(np.float64), y[sl].astype(np.float64)
+        assert np.isclose(sx[t], np.dot(xd, xd), rtol=1e-14)
+        assert np.isclose(sy[t], np.dot(yd, yd), rtol=1e-14)
+        assert np.isclose(se[t], np.dot(yd - r[sl], yd - r[sl]), rtol=1e-14)
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
