@@ -1,0 +1,167 @@
+/*
+ * fwht.h -- C ABI of the MI355X (gfx950) Walsh-Hadamard transform library.
+ *
+ * The operation (Lu, "Practical Tera-scale Walsh-Hadamard Transform",
+ * arXiv 1607.01039, section 2, Eq. 2): for an array x of 2^n entries,
+ *
+ *     W_k = sum_i (-1)^<k,i> x_i ,   <k,i> = parity of popcount(k & i),
+ *
+ * computed in place (section 3 restricts itself to in-place transforms),
+ * natural order, unnormalised for integers.  The threshold pass returns every
+ * coefficient with |W_k| > T together with its index position, the problem
+ * the paper's abstract and introduction pose for noisy sparse WHT.
+ *
+ * Conventions for every call:
+ *   - Pointers are plain addresses.  "device" means memory the GPU can read
+ *     and write (hipMalloc / torch CUDA tensors); "host" means ordinary CPU
+ *     memory; "pinned host" means hipHostMalloc'ed memory.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Device-path calls are
+ *     asynchronous and stream-ordered: they return after enqueueing work.
+ *   - The caller owns every buffer it passes.  The library allocates only its
+ *     own scratch (staging buffers of the streamed path, work lists and
+ *     cached graphs of the batched path) and keeps it until process exit.
+ *   - Arguments are validated before anything is enqueued; on a non-zero
+ *     return nothing has been enqueued and fwht_last_error() says why.
+ *     Faults inside kernels surface at the caller's next synchronisation.
+ *   - Integer arithmetic wraps modulo 2^32 (int32) or 2^64 (int64) at every
+ *     step; the result is exact whenever |W_k| < 2^31 (resp. 2^63), e.g. for
+ *     +-1 inputs with n <= 30.  It is never saturated.
+ *   - Functions are thread-safe with respect to each other except where
+ *     noted; calls that share a buffer must be ordered by the caller.
+ */
+#ifndef FWHT_H
+#define FWHT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FWHT_OK = 0,
+    FWHT_E_INVAL = 1,       /* bad pointer, alignment, dtype or size           */
+    FWHT_E_RANGE = 2,       /* n outside what the dtype / path supports         */
+    FWHT_E_CAPACITY = 3,    /* synchronous path: more hits than `cap`           */
+    FWHT_E_NOMEM = 4,       /* the library could not allocate its scratch       */
+    FWHT_E_HIP = 5,         /* a HIP runtime call failed (message has details)  */
+    FWHT_E_UNSUPPORTED = 6  /* valid request this build does not implement      */
+} fwht_status;
+
+typedef enum { FWHT_I32 = 0, FWHT_I64 = 1, FWHT_F32 = 2 } fwht_dtype;
+
+/* Arithmetic of float transforms.  FP16/BF16 round the data to half / bfloat16
+ * at the input of each radix-16 stage and multiply by the exact H_16 on the
+ * matrix cores with FP32 accumulation; storage stays FP32. */
+typedef enum {
+    FWHT_PREC_FP32 = 0,
+    FWHT_PREC_FP16_MFMA = 1,
+    FWHT_PREC_BF16_MFMA = 2
+} fwht_prec;
+
+/* Threshold request (problem statement of the abstract and section 1).
+ * All pointers are device pointers for device-path calls and host pointers
+ * for the synchronous pinned-host path of fwht_int. */
+typedef struct {
+    int64_t T;          /* integer data: keep k with |W_k| > T, |W_k| exact in 64 bits;
+                           T < 0 keeps every k                                       */
+    double Tf;          /* float data: keep k with |W_k| > Tf                          */
+    uint64_t *idx;      /* [cap] indices k of the hits, in no particular order         */
+    void *val;          /* [cap] W_k of the hits, element type of the data             */
+    uint64_t cap;       /* capacity of idx / val                                       */
+    uint64_t *count;    /* [1] set to the TRUE number of hits (may exceed cap; then    */
+                        /*     which hits were stored is unspecified)                  */
+} fwht_thresh_t;
+
+/* In-place unnormalised integer WHT of 2^n entries (section 2, Eq. 2; the
+ * stages of Fig. 1 regrouped into HBM passes).
+ *   data  : 2^n int32 (dtype FWHT_I32, n <= 30) or int64 (FWHT_I64) entries,
+ *           16-byte aligned.  A device pointer selects the in-HBM path
+ *           (n <= 34, asynchronous).  A pinned host pointer selects the
+ *           streamed Kronecker path (FWHT_I64 only, 10 <= n <= 40): the array
+ *           is split as H_{2^(n-L)} (x) H_{2^L} and both factors are applied
+ *           chunk by chunk through device staging buffers; the call is
+ *           synchronous with respect to the host.
+ *   th    : optional (NULL = none).  Fused into the last pass; *count is
+ *           zeroed by the call itself.  On the synchronous path the call
+ *           returns FWHT_E_CAPACITY when the true count exceeds cap.
+ * Errors: FWHT_E_INVAL (NULL/misaligned data, bad dtype, NULL threshold
+ * buffers), FWHT_E_RANGE (n < 0, int32 with n > 30, or beyond the path's
+ * limit), FWHT_E_NOMEM / FWHT_E_HIP from the streamed path's staging. */
+int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream);
+
+/* In-place float WHT of `batch` consecutive transforms of 2^n FP32 entries
+ * (device pointer, 16-byte aligned; 0 <= n <= 30, batch >= 1, batch * 2^n
+ * < 2^40).  normalize = 1 multiplies by 2^(-n/2) (a once-rounded FP32
+ * constant), making the transform orthonormal, symmetric and its own
+ * inverse.  prec = FWHT_PREC_FP32 for any n; the MFMA precisions need
+ * 4 <= n <= 16 (otherwise FWHT_E_UNSUPPORTED). */
+int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void *stream);
+
+/* In-place float WHT of `count` independent transforms of uneven sizes in
+ * one persistent launch replayed from a cached HIP graph.
+ *   data    : device FP32 buffer; transform t occupies
+ *             data[offsets[t] .. offsets[t] + 2^log2n[t]).
+ *   offsets : HOST array [count] of entry offsets (each a multiple of 4).
+ *   log2n   : HOST array [count], each in [0, 16].
+ * The work list is built from the host arrays on the first call with a given
+ * (data, count, normalize, prec, contents of offsets/log2n) and cached with
+ * its graph; later identical calls only replay the graph on `stream`.
+ * Transforms must not overlap.  Errors: FWHT_E_INVAL, FWHT_E_RANGE,
+ * FWHT_E_NOMEM, FWHT_E_HIP.  Not thread-safe with itself. */
+int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
+                 int normalize, int prec, void *stream);
+
+/* Stand-alone threshold pass over 2^n already-transformed device entries of
+ * dtype `dtype` (I32/I64 compare |W_k| > th->T exactly in 64 bits; F32
+ * compares |W_k| > th->Tf).  *th->count is zeroed by the call and receives
+ * the true number of hits; at most th->cap (index, value) pairs are stored,
+ * in no particular order.  Asynchronous on `stream`. */
+int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, void *stream);
+
+/* FP64 per-transform reductions used for the Parseval and error checks of
+ * float transforms (section 2: the orthonormal transform preserves the sum
+ * of squares).  For transform t (layout as in fwht_batched, HOST offsets and
+ * log2n), writes out[3t] = sum x^2, out[3t+1] = sum y^2 and
+ * out[3t+2] = sum (y - r)^2 (0 when r is NULL).  x, y: device FP32; r: device
+ * FP64 or NULL; out: device double[3 * count], overwritten. */
+int fwht_norms(const float *x, const float *y, const double *r, const int64_t *offsets,
+               const int32_t *log2n, int32_t count, double *out, void *stream);
+
+/* Override the pass schedule used for (dtype, n) by fwht_int / fwht_float,
+ * e.g. "C14,S14c6,S14c6" (comma-separated kernel variants, each optionally
+ * ":r" for the number of bits it takes).  spec = NULL restores the tuned
+ * default.  Used by the autotuner; returns FWHT_E_INVAL for an unknown
+ * variant or a schedule that does not cover n bits. */
+int fwht_set_schedule(int dtype, int n, const char *spec);
+
+/* Writes the schedule fwht_int / fwht_float would use for (dtype, n) into
+ * buf (NUL-terminated, truncated to len). */
+int fwht_get_schedule(int dtype, int n, char *buf, int len);
+
+/* Per-pass tracing (the per-phase runtime split of section 4.1, one entry per
+ * HBM pass).  While enabled, fwht_int / fwht_float record a HIP event on the
+ * call's stream before the first pass and after each pass.  fwht_trace_read
+ * waits for the events of the most recent traced call and writes the device
+ * time of each pass in milliseconds to ms[0..min(count, cap)), the number of
+ * passes to *count, and "variant:first_bit+bits,..." to names (may be NULL).
+ * Tracing state is process-wide. */
+int fwht_trace_enable(int on);
+int fwht_trace_read(float *ms, int cap, int *count, char *names, int names_len);
+
+/* Utility for measurement: plain device-to-device copy of `bytes` bytes
+ * (16-byte aligned pointers, bytes a multiple of 16), the reference kernel
+ * whose traffic calibrates the HBM counters.  Asynchronous. */
+int fwht_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char *fwht_last_error(void);
+
+/* Library version string. */
+const char *fwht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWHT_H */

@@ -1,0 +1,252 @@
+"""MI355X-native Walsh-Hadamard transform (Lu, arXiv 1607.01039).
+
+Python surface over the C ABI of ``libfwht.so`` (include/fwht.h).  torch is
+used for device memory and streams only; every transform, threshold pass and
+reduction runs in the library's HIP kernels.
+
+* ``fwht_int_(t, threshold=None, cap=...)`` -- in-place integer WHT (section 2,
+  Eq. 2) of a 1-D int32/int64 CUDA tensor of 2^n entries, optionally with the
+  fused pass returning every (k, W_k) with |W_k| > T, or of a pinned host
+  int64 tensor (streamed path, synchronous).
+* ``fwht_float_(t, normalize=True, precision="fp32")`` -- in-place float WHT
+  over the last dimension (2^n) of a float32 CUDA tensor.
+* ``fwht_batched_(data, offsets, log2n, ...)`` -- uneven batched transforms in
+  one persistent launch replayed from a cached HIP graph.
+* ``threshold(t, T, cap)`` -- stand-alone threshold pass.
+* ``fwht(x)`` -- differentiable orthonormal transform (autograd Function whose
+  backward is the same self-adjoint kernel).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import FWHTError
+
+PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
+              "bf16": _lib.FWHT_PREC_BF16_MFMA}
+
+__all__ = ["fwht_int_", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
+           "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
+           "FWHTError", "PRECISIONS"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(t=None):
+    torch = _torch()
+    if t is not None and not t.is_cuda:
+        return None
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _log2(size: int) -> int:
+    n = int(size).bit_length() - 1
+    if size <= 0 or (1 << n) != size:
+        raise ValueError(f"length {size} is not a power of two")
+    return n
+
+
+class Hits:
+    """Result of a threshold pass: indices and values of the hits (sorted by
+    index on request) plus the true count."""
+
+    def __init__(self, idx, val, count, cap):
+        self.idx, self.val, self.count, self.cap = idx, val, count, cap
+
+    @property
+    def overflow(self) -> bool:
+        return self.count > self.cap
+
+    def sorted(self):
+        order = np.argsort(self.idx, kind="stable")
+        return self.idx[order], self.val[order]
+
+
+def _thresh_buffers(dtype, cap, device):
+    torch = _torch()
+    idx = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
+    val = torch.zeros(max(cap, 1), dtype=dtype, device=device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=device)
+    return idx, val, cnt
+
+
+def _collect(idx, val, cnt, cap) -> Hits:
+    count = int(cnt.cpu().item())
+    k = min(count, cap)
+    return Hits(idx[:k].cpu().numpy().view(np.uint64).astype(np.int64), val[:k].cpu().numpy(), count, cap)
+
+
+def fwht_int_(t, threshold=None, cap: int = 1 << 16, sync: bool = True):
+    """In-place unnormalised integer WHT of a 1-D int32 / int64 tensor of 2^n entries.
+
+    With ``threshold=T`` the last pass also collects every (k, W_k) with
+    |W_k| > T; returns a ``Hits`` (after a stream sync when ``sync``), else
+    None.  A pinned host int64 tensor runs the streamed path synchronously.
+    """
+    torch = _torch()
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError("fwht_int_ needs a contiguous 1-D tensor")
+    dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64}.get(t.dtype)
+    if dt is None:
+        raise TypeError("fwht_int_ needs int32 or int64")
+    n = _log2(t.numel())
+    L = _lib.lib()
+    th = None
+    bufs = None
+    if threshold is not None:
+        device = t.device if t.is_cuda else "cpu"
+        if t.is_cuda:
+            bufs = _thresh_buffers(t.dtype, cap, device)
+        else:
+            bufs = tuple(b.pin_memory() for b in _thresh_buffers(t.dtype, cap, "cpu"))
+        th = _lib.fwht_thresh_t(int(threshold), 0.0, bufs[0].data_ptr(), bufs[1].data_ptr(), cap,
+                                bufs[2].data_ptr())
+    stream = _stream_ptr(t) if t.is_cuda else C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = L.fwht_int(C.c_void_p(t.data_ptr()), dt, n, C.byref(th) if th else None, stream)
+    if rc == _lib.FWHT_E_CAPACITY and bufs is not None:
+        return _collect(*bufs, cap)
+    _lib.check(rc)
+    if bufs is None:
+        return None
+    if not sync:
+        return bufs
+    if t.is_cuda:
+        torch.cuda.current_stream().synchronize()
+    return _collect(*bufs, cap)
+
+
+def fwht_float_(t, normalize: bool = True, precision: str = "fp32"):
+    """In-place float WHT over the last dimension (2^n) of a float32 CUDA tensor."""
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("fwht_float_ needs a contiguous float32 CUDA tensor")
+    n = _log2(t.shape[-1])
+    batch = t.numel() >> n
+    _lib.check(_lib.lib().fwht_float(C.c_void_p(t.data_ptr()), n, batch, int(bool(normalize)),
+                                     PRECISIONS[precision], _stream_ptr(t)))
+    return t
+
+
+def fwht_batched_(data, offsets, log2n, normalize: bool = True, precision: str = "fp32"):
+    """In-place WHT of uneven transforms packed in a float32 CUDA tensor.
+
+    ``offsets`` (int64) and ``log2n`` (int32) are host arrays (numpy or CPU
+    tensors): transform t is data[offsets[t] : offsets[t] + 2^log2n[t]].
+    """
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+    if off.shape != lg.shape:
+        raise ValueError("offsets and log2n must have the same length")
+    _lib.check(_lib.lib().fwht_batched(C.c_void_p(data.data_ptr()), off.ctypes.data_as(C.c_void_p),
+                                       lg.ctypes.data_as(C.c_void_p), len(off), int(bool(normalize)),
+                                       PRECISIONS[precision], _stream_ptr(data)))
+    return data
+
+
+def threshold(t, T, cap: int = 1 << 16) -> Hits:
+    """Stand-alone pass: every (k, t[k]) with |t[k]| > T over a 1-D CUDA tensor of 2^n entries."""
+    torch = _torch()
+    dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64, torch.float32: _lib.FWHT_F32}[t.dtype]
+    n = _log2(t.numel())
+    idx, val, cnt = _thresh_buffers(t.dtype, cap, t.device)
+    if dt == _lib.FWHT_F32:
+        th = _lib.fwht_thresh_t(0, float(T), idx.data_ptr(), val.data_ptr(), cap, cnt.data_ptr())
+    else:
+        th = _lib.fwht_thresh_t(int(T), 0.0, idx.data_ptr(), val.data_ptr(), cap, cnt.data_ptr())
+    _lib.check(_lib.lib().fwht_threshold(C.c_void_p(t.data_ptr()), dt, n, C.byref(th), _stream_ptr(t)))
+    torch.cuda.current_stream().synchronize()
+    return _collect(idx, val, cnt, cap)
+
+
+def norms(x, y, offsets, log2n, r=None):
+    """FP64 per-transform (sum x^2, sum y^2, sum (y - r)^2) on the GPU -> (count, 3) float64 tensor."""
+    torch = _torch()
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+    out = torch.empty((len(off), 3), dtype=torch.float64, device=x.device)
+    _lib.check(_lib.lib().fwht_norms(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                     C.c_void_p(r.data_ptr()) if r is not None else None,
+                                     off.ctypes.data_as(C.c_void_p), lg.ctypes.data_as(C.c_void_p),
+                                     len(off), C.c_void_p(out.data_ptr()), _stream_ptr(x)))
+    return out
+
+
+def trace_enable(on: bool = True) -> None:
+    """Record a HIP event around every pass of later fwht_int_/fwht_float_ calls."""
+    _lib.check(_lib.lib().fwht_trace_enable(int(bool(on))))
+
+
+def trace_read():
+    """[(pass name, device ms)] of the most recent traced call."""
+    ms = (C.c_float * 64)()
+    cnt = C.c_int(0)
+    names = C.create_string_buffer(4096)
+    _lib.check(_lib.lib().fwht_trace_read(ms, 64, C.byref(cnt), names, 4096))
+    nm = names.value.decode().split(",") if cnt.value else []
+    return list(zip(nm, [float(ms[i]) for i in range(cnt.value)]))
+
+
+def copy_(dst, src) -> None:
+    """Plain device copy kernel (reference kernel for bandwidth calibration)."""
+    nbytes = src.numel() * src.element_size()
+    _lib.check(_lib.lib().fwht_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                                    _stream_ptr(src)))
+
+
+def set_schedule(dtype: str, n: int, spec):
+    dt = {"int32": _lib.FWHT_I32, "int64": _lib.FWHT_I64, "float32": _lib.FWHT_F32}[dtype]
+    _lib.check(_lib.lib().fwht_set_schedule(dt, n, spec.encode() if spec else None))
+
+
+def get_schedule(dtype: str, n: int) -> str:
+    dt = {"int32": _lib.FWHT_I32, "int64": _lib.FWHT_I64, "float32": _lib.FWHT_F32}[dtype]
+    buf = C.create_string_buffer(256)
+    _lib.check(_lib.lib().fwht_get_schedule(dt, n, buf, 256))
+    return buf.value.decode()
+
+
+def _make_function():
+    torch = _torch()
+
+    class FWHTFunction(torch.autograd.Function):
+        """Orthonormal WHT over the last dimension.  Y = 2^(-n/2) H is symmetric
+        and orthogonal, so the adjoint applied in backward is Y itself: the
+        same kernel runs on the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, x, precision="fp32"):
+            ctx.precision = precision
+            y = x.contiguous().clone()
+            fwht_float_(y, True, precision)
+            return y
+
+        @staticmethod
+        def backward(ctx, g):
+            gx = g.contiguous().clone()
+            fwht_float_(gx, True, ctx.precision)
+            return gx, None
+
+    return FWHTFunction
+
+
+_fn = None
+
+
+def __getattr__(name):
+    global _fn
+    if name == "FWHTFunction":
+        if _fn is None:
+            _fn = _make_function()
+        return _fn
+    raise AttributeError(name)
+
+
+def fwht(x, precision: str = "fp32"):
+    """Differentiable orthonormal WHT over the last dimension of a float32 CUDA tensor."""
+    return __getattr__("FWHTFunction").apply(x, precision)

@@ -1,0 +1,59 @@
+// fwht_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fwht.h"
+
+namespace fwht {
+
+struct PassArgs;
+
+// One compiled tile-kernel variant (see wht_tile.hpp): tiles of 2^TB entries,
+// 2^CB contiguous columns, NT threads; COLS = contiguous pass.
+struct Variant {
+    const char *name;
+    int TB, CB, NT;
+    bool cols;
+    hipError_t (*launch)(void *buf, const PassArgs &a, hipStream_t s);
+};
+
+// One pass of a schedule: variant `v` transforms global bits [lo, lo + r).
+struct Pass {
+    const Variant *v;
+    int lo, r;
+};
+
+// What the last pass applies before storing.
+struct Epilogue {
+    int do_scale = 0;
+    float scale = 1.f;
+    int thresh = 0;
+    int64_t T = 0;
+    float Tf = 0.f;
+    uint64_t *idx = nullptr;
+    void *val = nullptr;
+    uint64_t cap = 0;
+    uint64_t *count = nullptr;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+const std::vector<Variant> &registry(int dtype);
+bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass> &out, std::string &why);
+std::string schedule_for(int dtype, int n);
+const std::string *tuned_schedule(int dtype, int n);
+int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s);
+int zero_count(uint64_t *count, hipStream_t s);
+float float_threshold(double T);
+
+// streamed Kronecker path (pinned host data), fwht_stream.hip
+int streamed_int(void *host, int dtype, int n, const fwht_thresh_t *th, hipStream_t s);
+// MFMA uniform-size float path, fwht_batched.hip
+int mfma_uniform(float *data, int n, uint64_t batch, int normalize, int prec, hipStream_t s);
+
+}  // namespace fwht

@@ -1,0 +1,408 @@
+// wht_tile.hpp -- one HBM pass of the in-place Walsh-Hadamard transform on gfx950.
+//
+// A pass applies the radix-2 butterflies (a, b) -> (a + b, a - b) of the stages
+// whose index bits fall in one bit range (section 3, Fig. 1: stage k pairs the
+// entries pt and pt + 2^k).  Stages on distinct bits commute, so a transform of
+// 2^n entries is any sequence of passes that together cover bits 0..n-1
+// (the regrouping that Fig. 2 and Fig. 3 use across cores and disk passes).
+//
+// The array is viewed as rows of 2^b entries.  One workgroup owns a tile of
+// 2^TB entries: 2^CB contiguous columns (tile bits 0..CB-1) of 2^(TB-CB)
+// consecutive rows (tile bits CB..TB-1, global bits b..b+TB-CB-1).
+//   * contiguous pass (b = CB, COLS): the tile is 2^TB consecutive entries and
+//     all TB tile bits may be transformed;
+//   * strided pass (b > CB): only the row bits are transformed; the CB column
+//     bits give 2^CB * sizeof(S) contiguous bytes per row segment.
+// Which tile bits are transformed is a run-time mask (`act`), so the same
+// kernel also serves short transforms (several per tile) and partial passes.
+//
+// Inside the tile, every thread keeps E = 2^TB / NT entries in registers.  A
+// "layout" says which tile bits are register bits (mask M); the other bits
+// index the thread (lanes take the lowest ones, so a wave touches contiguous
+// memory).  The kernel walks a compile-time list of layouts: L0 (vector-load
+// layout: the low VB bits + the top bits are register bits), then groups of
+// K = log2 E untransformed bits in ascending order.  Within a layout the
+// butterflies on register bits are plain VALU add/sub; between layouts the
+// tile is transposed through LDS, padded by one word per 32 so that every
+// access pattern used here is free of bank conflicts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace fwht {
+
+// ---------------------------------------------------------------- compile time
+constexpr int cpopc(uint32_t m) { int c = 0; while (m) { c += m & 1u; m >>= 1; } return c; }
+constexpr int clog2(uint32_t v) { int r = 0; while (v > 1) { v >>= 1; ++r; } return r; }
+constexpr int nth_bit(uint32_t m, int q)
+{
+    for (int b = 0; b < 32; ++b)
+        if ((m >> b) & 1u) { if (q == 0) return b; --q; }
+    return 31;
+}
+constexpr uint32_t cpdep(uint32_t x, uint32_t m)
+{
+    uint32_t r = 0;
+    int q = 0;
+    for (int b = 0; b < 32; ++b)
+        if ((m >> b) & 1u) { if ((x >> q) & 1u) r |= 1u << b; ++q; }
+    return r;
+}
+constexpr uint32_t lowmask(int k) { return k >= 32 ? 0xffffffffu : ((1u << k) - 1u); }
+
+struct LayoutList {
+    uint32_t m[8];      // register bits of each layout
+    uint32_t fresh[8];  // bits a layout transforms (its own group, not its filler)
+    int n;
+};
+
+// L0 = low VB bits + top (K - VB) bits; then the remaining candidate bits in
+// ascending groups of K, the last group topped up with the highest other bits.
+constexpr LayoutList make_layouts(int TB, int CB, int K, int VB, bool cols)
+{
+    LayoutList L{};
+    const uint32_t full = lowmask(TB);
+    const int top = K - VB;
+    L.m[0] = lowmask(VB) | (lowmask(top) << (TB - top));
+    L.n = 1;
+    const uint32_t cand = cols ? full : (full & ~lowmask(CB));
+    L.fresh[0] = L.m[0] & cand;
+    uint32_t rem = cand & ~L.m[0];
+    while (rem) {
+        uint32_t g = 0;
+        int c = 0;
+        for (int b = 0; b < TB && c < K; ++b)
+            if ((rem >> b) & 1u) { g |= 1u << b; ++c; }
+        rem &= ~g;
+        L.fresh[L.n] = g;
+        for (int b = TB - 1; b >= 0 && c < K; --b)
+            if (!((g >> b) & 1u)) { g |= 1u << b; ++c; }
+        L.m[L.n++] = g;
+    }
+    return L;
+}
+
+// A layout is store-friendly when its lowest non-register bits are the low
+// bits of the tile, i.e. the lanes of a wave write consecutive entries.
+constexpr bool lanes_contiguous(uint32_t m, int nlanebits)
+{
+    return (m & lowmask(nlanebits)) == 0;
+}
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <uint32_t MASK>
+__device__ __forceinline__ uint32_t pdep_rt(uint32_t x)
+{
+    uint32_t r = 0;
+    int q = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b)
+        if ((MASK >> b) & 1u) { r |= ((x >> q) & 1u) << b; ++q; }
+    return r;
+}
+
+// ------------------------------------------------------------------ pass args
+struct PassArgs {
+    uint64_t total;      // entries in the array (batch * 2^n)
+    uint64_t colblocks;  // 2^(b - CB): column blocks per row
+    uint64_t ntiles;     // tiles in this pass
+    uint32_t b;          // log2 of the row stride
+    uint32_t act;        // transformed tile bits
+    // epilogue (last pass only)
+    int32_t do_scale;    // float: multiply by `scale`
+    float scale;
+    int32_t thresh;      // emit (k, y_k) with |y_k| > T
+    int64_t T;           // integer threshold (T < 0: every entry)
+    float Tf;            // float threshold, rounded toward -inf from double
+    unsigned long long *hit_idx;
+    void *hit_val;
+    uint64_t cap;
+    unsigned long long *count;
+};
+
+template <class S> struct Arith;
+template <> struct Arith<uint32_t> {
+    __device__ static bool above(uint32_t v, const PassArgs &a)
+    {
+        int32_t s = (int32_t)v;
+        uint32_t mag = s < 0 ? 0u - v : v;
+        return a.T < 0 || (int64_t)mag > a.T;
+    }
+};
+template <> struct Arith<uint64_t> {
+    __device__ static bool above(uint64_t v, const PassArgs &a)
+    {
+        int64_t s = (int64_t)v;
+        uint64_t mag = s < 0 ? 0ull - v : v;
+        return a.T < 0 || mag > (uint64_t)a.T;
+    }
+};
+template <> struct Arith<float> {
+    __device__ static bool above(float v, const PassArgs &a) { return fabsf(v) > a.Tf; }
+};
+
+// Wave-aggregated append of one (index, value) hit per lane with `hit` set.
+template <class S>
+__device__ __forceinline__ void emit_hits(bool hit, uint64_t k, S v, const PassArgs &a)
+{
+    uint64_t m = __ballot(hit);
+    if (m == 0) return;
+    const uint32_t lane = __lane_id();
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if ((int)lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    if (hit) {
+        unsigned long long slot = base + below;
+        if (slot < a.cap) {
+            a.hit_idx[slot] = k;
+            ((S *)a.hit_val)[slot] = v;
+        }
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void bfly(S &x, S &y)
+{
+    S a = x, b = y;
+    x = a + b;
+    y = a - b;
+}
+
+// Butterflies on the register bits of layout M that it owns (FRESH) and the
+// pass transforms (act).
+template <class S, uint32_t M, uint32_t FRESH, int E>
+__device__ __forceinline__ void reg_stages(S (&v)[E], uint32_t act)
+{
+    constexpr int K = clog2(E);
+    static_for<0, K>([&](auto Q) {
+        constexpr int q = decltype(Q)::value;
+        constexpr int bit = nth_bit(M, q);
+        if (((FRESH >> bit) & 1u) && ((act >> bit) & 1u)) {
+#pragma unroll
+            for (int j = 0; j < E; ++j)
+                if (!((j >> q) & 1)) bfly(v[j], v[j | (1 << q)]);
+        }
+    });
+}
+
+__device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
+
+template <int TB, int CB, int NT, bool COLS, class S>
+struct TileKernel {
+    static constexpr int E = (1 << TB) / NT;
+    static constexpr int K = clog2(E);
+    static constexpr int VEC = 16 / (int)sizeof(S);
+    static constexpr int VB = clog2(VEC);
+    static constexpr int R = TB - CB;
+    static constexpr LayoutList LS = make_layouts(TB, CB, K, VB, COLS);
+    static constexpr uint32_t FULL = lowmask(TB);
+    static constexpr int LDS_ELEMS = (1 << TB) + (1 << TB) / 32;
+    static_assert(E * NT == (1 << TB), "tile must split evenly");
+    static_assert(E >= VEC, "a thread must hold at least one vector");
+    static_assert(K - VB <= R, "top register bits must be row bits");
+    static_assert(CB >= VB + 2, "a row segment must be at least 4 vectors");
+    static_assert(NT % 64 == 0, "whole waves");
+    static_assert(LS.n <= 8, "too many layouts");
+    // The lanes of the store layout must write whole 64-lane runs.
+    // Lanes of a store-friendly layout write >= 256 contiguous bytes.
+    static constexpr int SLB = 8 - clog2(sizeof(S));
+    static_assert(lanes_contiguous(LS.m[LS.n - 1], SLB) || LS.n == 1, "store layout");
+
+    // Global offset of tile index `idx` (row part scaled by the row stride).
+    __device__ static __forceinline__ uint64_t goff(uint64_t base, uint32_t idx, uint32_t b)
+    {
+        return base + ((uint64_t)(idx >> CB) << b) + (idx & lowmask(CB));
+    }
+
+    template <int P>
+    __device__ static __forceinline__ void to_lds(S *lds, const S (&v)[E], uint32_t t)
+    {
+        constexpr uint32_t M = LS.m[P];
+        const uint32_t tb = lds_pad(pdep_rt<FULL & ~M>(t));
+        static_for<0, E>([&](auto J) {
+            constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, M);
+            lds[tb + jp + (jp >> 5)] = v[decltype(J)::value];
+        });
+    }
+
+    template <int P>
+    __device__ static __forceinline__ void from_lds(const S *lds, S (&v)[E], uint32_t t)
+    {
+        constexpr uint32_t M = LS.m[P];
+        const uint32_t tb = lds_pad(pdep_rt<FULL & ~M>(t));
+        static_for<0, E>([&](auto J) {
+            constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, M);
+            v[decltype(J)::value] = lds[tb + jp + (jp >> 5)];
+        });
+    }
+
+    __device__ static void run(S *__restrict__ buf, const PassArgs &a)
+    {
+        __shared__ S lds[LDS_ELEMS];
+        const uint32_t t = threadIdx.x;
+        for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+            const uint64_t g = tile / a.colblocks;
+            const uint64_t cb = tile - g * a.colblocks;
+            const uint64_t base = ((g << R) << a.b) + (cb << CB);
+            const bool full = (((g + 1) << R) << a.b) <= a.total;
+
+            S v[E];
+            // ---- load in layout L0: VEC consecutive entries per 16-byte access
+            {
+                constexpr uint32_t M0 = LS.m[0];
+                const uint32_t tp = pdep_rt<FULL & ~M0>(t);
+                static_for<0, E / VEC>([&](auto JT) {
+                    constexpr int jt = decltype(JT)::value;
+                    constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
+                    const uint64_t off = goff(base, jp | tp, a.b);
+                    if (full || off + VEC <= a.total) {
+                        const uint4 q = *reinterpret_cast<const uint4 *>(buf + off);
+                        const S *qs = reinterpret_cast<const S *>(&q);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            v[jt * VEC + e] = (off + e < a.total) ? buf[off + e] : S(0);
+                    }
+                });
+            }
+            reg_stages<S, LS.m[0], LS.fresh[0], E>(v, a.act);
+
+            // ---- remaining layouts, skipping those without transformed bits
+            int cur = 0;
+            bool wrote = false;
+            static_for<1, LS.n>([&](auto PP) {
+                constexpr int P = decltype(PP)::value;
+                if (a.act & LS.fresh[P]) {
+                    if (wrote) __syncthreads();
+                    dispatch_to_lds(lds, v, t, cur);
+                    __syncthreads();
+                    from_lds<P>(lds, v, t);
+                    wrote = true;
+                    cur = P;
+                    reg_stages<S, LS.m[P], LS.fresh[P], E>(v, a.act);
+                }
+            });
+            // The store layout: L0, or any layout whose lanes are contiguous.
+            if (cur != 0 && !store_ok(cur)) {
+                if (wrote) __syncthreads();
+                dispatch_to_lds(lds, v, t, cur);
+                __syncthreads();
+                from_lds<0>(lds, v, t);
+                cur = 0;
+            }
+            if (cur == 0) store_vec(buf, v, t, base, full, a);
+            else dispatch_store(buf, v, t, base, full, a, cur);
+            __syncthreads();  // the next tile reuses the LDS buffer
+        }
+    }
+
+    __device__ static __forceinline__ bool store_ok(int p)
+    {
+        bool ok = false;
+        static_for<0, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if (P == p) ok = lanes_contiguous(LS.m[P], SLB);
+        });
+        return ok;
+    }
+
+    __device__ static __forceinline__ void dispatch_to_lds(S *lds, const S (&v)[E], uint32_t t, int p)
+    {
+        static_for<0, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if (P == p) to_lds<P>(lds, v, t);
+        });
+    }
+
+    __device__ static __forceinline__ S epi(S x, const PassArgs &a)
+    {
+        if constexpr (std::is_same<S, float>::value) {
+            if (a.do_scale) x *= a.scale;
+        }
+        return x;
+    }
+
+    __device__ static __forceinline__ void store_vec(S *__restrict__ buf, S (&v)[E], uint32_t t,
+                                                     uint64_t base, bool full, const PassArgs &a)
+    {
+        constexpr uint32_t M0 = LS.m[0];
+        const uint32_t tp = pdep_rt<FULL & ~M0>(t);
+        static_for<0, E / VEC>([&](auto JT) {
+            constexpr int jt = decltype(JT)::value;
+            constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
+            const uint64_t off = goff(base, jp | tp, a.b);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = epi(v[jt * VEC + e], a);
+            if (a.thresh) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const bool in = full || off + e < a.total;
+                    emit_hits<S>(in && Arith<S>::above(v[jt * VEC + e], a), off + e, v[jt * VEC + e], a);
+                }
+            }
+            if (full || off + VEC <= a.total) {
+                uint4 q;
+                S *qs = reinterpret_cast<S *>(&q);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
+                *reinterpret_cast<uint4 *>(buf + off) = q;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (off + e < a.total) buf[off + e] = v[jt * VEC + e];
+            }
+        });
+    }
+
+    template <int P>
+    __device__ static __forceinline__ void store_layout(S *__restrict__ buf, S (&v)[E], uint32_t t,
+                                                        uint64_t base, bool full, const PassArgs &a)
+    {
+        constexpr uint32_t M = LS.m[P];
+        const uint32_t tp = pdep_rt<FULL & ~M>(t);
+        static_for<0, E>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr uint32_t jp = cpdep((uint32_t)j, M);
+            const uint64_t off = goff(base, jp | tp, a.b);
+            const S x = epi(v[j], a);
+            const bool in = full || off < a.total;
+            if (a.thresh) emit_hits<S>(in && Arith<S>::above(x, a), off, x, a);
+            if (in) buf[off] = x;
+        });
+    }
+
+    __device__ static __forceinline__ void dispatch_store(S *__restrict__ buf, S (&v)[E], uint32_t t,
+                                                          uint64_t base, bool full, const PassArgs &a, int p)
+    {
+        static_for<1, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if constexpr (lanes_contiguous(LS.m[P], SLB)) {
+                if (P == p) store_layout<P>(buf, v, t, base, full, a);
+            }
+        });
+    }
+};
+
+template <int TB, int CB, int NT, bool COLS, class S>
+__global__ void __launch_bounds__(NT) wht_tile_kernel(S *__restrict__ buf, PassArgs a)
+{
+    TileKernel<TB, CB, NT, COLS, S>::run(buf, a);
+}
+
+}  // namespace fwht

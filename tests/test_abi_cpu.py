@@ -1,0 +1,106 @@
+"""The C-ABI library loads, exports every declared symbol and validates its
+arguments before touching the GPU (runs without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fwht.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fwht_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1607_01039_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_1607_01039_amd import _lib
+    decl = declared_symbols()
+    assert len(decl) >= 10
+    assert set(decl) == set(_lib.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_version(L):
+    assert L.fwht_version().startswith(b"fwht-gfx950")
+
+
+def _buf():
+    # 16-byte aligned host buffer; validation fails before it is ever used.
+    b = (C.c_uint8 * 64)()
+    base = C.addressof(b)
+    return b, base + (-base % 16)
+
+
+def test_int_validation(L):
+    from paper_1607_01039_amd import _lib
+    keep, p = _buf()
+    assert L.fwht_int(None, 0, 4, None, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_int(C.c_void_p(p + 4), 0, 4, None, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_int(C.c_void_p(p), 7, 4, None, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_int(C.c_void_p(p), _lib.FWHT_I32, -1, None, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_int(C.c_void_p(p), _lib.FWHT_I32, 31, None, None) == _lib.FWHT_E_RANGE
+    assert b"n <= 30" in L.fwht_last_error()
+    th = _lib.fwht_thresh_t(5, 0.0, None, None, 4, None)
+    assert L.fwht_int(C.c_void_p(p), _lib.FWHT_I32, 4, C.byref(th), None) == _lib.FWHT_E_INVAL
+    th = _lib.fwht_thresh_t(5, 0.0, None, None, 4, p)
+    assert L.fwht_int(C.c_void_p(p), _lib.FWHT_I32, 4, C.byref(th), None) == _lib.FWHT_E_INVAL
+
+
+def test_float_validation(L):
+    from paper_1607_01039_amd import _lib
+    keep, p = _buf()
+    assert L.fwht_float(None, 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_float(C.c_void_p(p), 31, 1, 1, 0, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_float(C.c_void_p(p), 4, 0, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_float(C.c_void_p(p), 30, 1 << 12, 1, 0, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_float(C.c_void_p(p), 4, 1, 1, 9, None) == _lib.FWHT_E_INVAL
+
+
+def test_threshold_validation(L):
+    from paper_1607_01039_amd import _lib
+    keep, p = _buf()
+    assert L.fwht_threshold(C.c_void_p(p), 0, 4, None, None) == _lib.FWHT_E_INVAL
+    th = _lib.fwht_thresh_t(5, 0.0, p, p, 4, p)
+    assert L.fwht_threshold(C.c_void_p(p), 9, 4, C.byref(th), None) == _lib.FWHT_E_INVAL
+    assert L.fwht_threshold(C.c_void_p(p), 0, -2, C.byref(th), None) == _lib.FWHT_E_RANGE
+
+
+def test_schedule_parsing(L):
+    from paper_1607_01039_amd import _lib
+    ok = [(0, 30, b"C14,S14c6,S14c6"), (0, 20, b"C12,S14c6:8"), (1, 25, b"C13,S13c5,S13c5:4"),
+          (2, 16, b"C15:10,S12c5:6")]
+    for dt, n, spec in ok:
+        assert L.fwht_set_schedule(dt, n, spec) == 0, (spec, L.fwht_last_error())
+        buf = C.create_string_buffer(128)
+        assert L.fwht_get_schedule(dt, n, buf, 128) == 0 and buf.value == spec
+        assert L.fwht_set_schedule(dt, n, None) == 0
+    bad = [(0, 30, b"C14,S14c6"), (0, 20, b"S14c6,C14"), (0, 20, b"X9"), (0, 20, b"C14:0,S14c6"),
+           (0, 20, b"C12:3,S14c6,S14c6")]
+    for dt, n, spec in bad:
+        assert L.fwht_set_schedule(dt, n, spec) == _lib.FWHT_E_INVAL, spec
+
+
+def test_default_schedules_cover_every_n(L):
+    for dt, nmax in ((0, 30), (1, 34), (2, 30)):
+        for n in range(1, nmax + 1):
+            buf = C.create_string_buffer(128)
+            assert L.fwht_get_schedule(dt, n, buf, 128) == 0
+            assert L.fwht_set_schedule(dt, n, buf.value) == 0, (dt, n, buf.value, L.fwht_last_error())
+            assert L.fwht_set_schedule(dt, n, None) == 0
+
+
+def test_product_does_not_import_oracle():
+    import subprocess, sys
+    code = ("import sys, paper_1607_01039_amd as p; p._lib.lib();"
+            "assert 'oracle' not in sys.modules, 'product imported the oracle'")
+    subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)

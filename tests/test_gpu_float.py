@@ -1,0 +1,72 @@
+"""GPU parity of the FP32 float transform against the FP64 oracle.
+
+Tolerance (derived from the arithmetic): each of the n radix-2 stages rounds
+every entry once to FP32 (unit roundoff u = 2^-24), and the stages are
+orthogonal up to a factor sqrt(2), so the normwise relative error of the
+unnormalised result is at most about n * u * sqrt(2) plus one rounding of the
+scale.  The tests gate at (n + 2) * 2^-23, twice that bound.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1607_01039_amd as F
+    F._lib.lib()
+    return F
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def tol(n):
+    return (n + 2) * 2.0 ** -23
+
+
+def normwise(y, ref):
+    y = y.reshape(-1, ref.shape[-1]).astype(np.float64)
+    r = ref.reshape(-1, ref.shape[-1])
+    return float(np.max(np.linalg.norm(y - r, axis=1) / np.maximum(np.linalg.norm(r, axis=1), 1e-300)))
+
+
+@pytest.mark.parametrize("n,batch", [(0, 5), (1, 3), (2, 1), (3, 7), (5, 33), (8, 3), (11, 2), (12, 5),
+                                     (13, 3), (14, 2), (15, 1), (16, 3), (19, 1), (20, 2), (22, 1)])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_float_matches_oracle(F, O, n, batch, normalize):
+    x = synth.normal((batch, 1 << n), 100 * n + batch)
+    t = _dev(x)
+    F.fwht_float_(t, normalize=normalize)
+    ref = O.wht_batch(x, n, normalize)
+    assert normwise(t.cpu().numpy(), ref) <= tol(n)
+
+
+def test_float_config_autograd_shape(F, O):
+    # 256 x 2^20 orthonormal (the autograd workload), sampled rows vs the oracle.
+    n, B = 20, 256
+    x = synth.normal((B, 1 << n), 5)
+    t = _dev(x)
+    F.fwht_float_(t, normalize=True)
+    y = t.cpu().numpy()
+    for r in (0, 77, 255):
+        ref = O.wht_batch(x[r:r + 1], n, True)
+        assert normwise(y[r:r + 1], ref) <= tol(n)
+    # Parseval per row
+    assert np.allclose((y.astype(np.float64) ** 2).sum(1), (x.astype(np.float64) ** 2).sum(1), rtol=1e-5)
+
+
+def test_float_integer_inputs_exact(F, O):
+    # Small-integer inputs stay exactly representable: bit-exact, unnormalised.
+    n = 18
+    x = synth.ints(1 << n, 4, -8, 8, dtype=np.int64).astype(np.float32)
+    t = _dev(x)
+    F.fwht_float_(t, normalize=False)
+    assert np.array_equal(t.cpu().numpy().astype(np.float64), O.wht_fig1(x))

@@ -1,0 +1,192 @@
+"""GPU parity of the integer transform and the threshold pass against the oracle.
+
+Integer results must be bit-exact (wrap-around mod 2^32 / 2^64).  Hit lists
+are compared as sets of (k, W_k) with the true count.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1607_01039_amd as F
+    F._lib.lib()
+    return F
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _run_int(F, x, **kw):
+    t = _dev(x)
+    hits = F.fwht_int_(t, **kw)
+    return t.cpu().numpy(), hits
+
+
+@pytest.mark.parametrize("n", list(range(0, 23)))
+def test_int32_every_n(F, O, n):
+    x = synth.ints(1 << n, 1000 + n, -(1 << 20), 1 << 20, dtype=np.int32)
+    y, _ = _run_int(F, x)
+    assert np.array_equal(y, O.wht_fig1(x))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 8, 11, 12, 13, 14, 17, 20, 21])
+def test_int64_every_n(F, O, n):
+    x = synth.ints(1 << n, 2000 + n, -(1 << 40), 1 << 40, dtype=np.int64)
+    y, _ = _run_int(F, x)
+    assert np.array_equal(y, O.wht_fig1(x))
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 12])
+def test_int_matches_definition(F, O, n):
+    x = synth.ints(1 << n, 3000 + n, -50, 50, dtype=np.int32)
+    y, _ = _run_int(F, x)
+    assert np.array_equal(y.astype(np.int64), O.wht_def(x.astype(np.int64)))
+
+
+def test_int32_wraps_like_oracle(F, O):
+    n = 14
+    x = synth.ints(1 << n, 7, -(1 << 31), (1 << 31) - 1, dtype=np.int32)
+    y, _ = _run_int(F, x)
+    assert np.array_equal(y, O.wht_fig1(x))
+
+
+SCHEDULES_I32 = {
+    20: ["C12,S12c5:7,S14c6:1", "C14:6,S14c6:8,S13c6:6", "C15:15,S12c5:5", "C13:9,S15c6:9,S13c5:2",
+         "C12:6,S12c5:7,S12c5:7"],
+    26: ["C12,S14c6,S14c6:6", "C15,S15c6:9,S12c5:2", "C14,S13c6:6,S13c6:6"],
+}
+SCHEDULES_I64 = {
+    20: ["C11,S12c4:8,S13c5:1", "C14:6,S14c5,S12c4:5", "C13,S14c4:7"],
+}
+
+
+@pytest.mark.parametrize("n,spec", [(n, s) for n, ss in SCHEDULES_I32.items() for s in ss])
+def test_every_schedule_gives_the_same_bits_i32(F, O, n, spec):
+    x = synth.signs(1 << n, 5 + n)
+    F.set_schedule("int32", n, spec)
+    try:
+        y, _ = _run_int(F, x)
+    finally:
+        F.set_schedule("int32", n, None)
+    assert np.array_equal(y, O.wht_fig2(x, 3))
+
+
+@pytest.mark.parametrize("n,spec", [(n, s) for n, ss in SCHEDULES_I64.items() for s in ss])
+def test_every_schedule_gives_the_same_bits_i64(F, O, n, spec):
+    x = synth.ints(1 << n, 6 + n, -(1 << 35), 1 << 35, dtype=np.int64)
+    F.set_schedule("int64", n, spec)
+    try:
+        y, _ = _run_int(F, x)
+    finally:
+        F.set_schedule("int64", n, None)
+    assert np.array_equal(y, O.wht_fig1(x))
+
+
+def test_config_n24_signs(F, O):
+    # +-1 signs, n = 24, seed 1: full element-by-element parity.
+    x = synth.signs(1 << 24, 1)
+    y, _ = _run_int(F, x)
+    assert np.array_equal(y, O.wht_fig2(x, 3))
+
+
+@pytest.mark.parametrize("n,p,seed,T", [(16, 0.45, 2, 6 * 256), (18, 0.3, 3, 4 * 512), (21, 0.45, 4, 5 * 1448),
+                                        (13, 0.45, 5, -1), (12, 0.45, 6, 0)])
+def test_fused_threshold_matches_oracle(F, O, n, p, seed, T):
+    x, s, err = synth.planted(n, seed, p)
+    y, hits = _run_int(F, x, threshold=T, cap=1 << n)
+    ref = O.wht_fig1(x)
+    assert np.array_equal(y, ref)
+    ridx, rval, rcnt = O.threshold(ref, T)
+    assert hits.count == rcnt
+    gi, gv = hits.sorted()
+    assert np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+    if T >= 0 and T < (1 << n) - 2 * err:
+        assert s in set(gi.tolist())
+
+
+def test_fused_threshold_capacity_overflow(F, O):
+    n = 12
+    x = synth.signs(1 << n, 9)
+    y, hits = _run_int(F, x, threshold=-1, cap=100)
+    assert hits.count == 1 << n and len(hits.idx) == 100
+    ref = O.wht_fig1(x)
+    assert np.array_equal(ref[hits.idx], hits.val)
+    assert len(set(hits.idx.tolist())) == 100
+
+
+def test_int64_threshold(F, O):
+    n = 17
+    x, s, err = synth.planted(n, 8, 0.4, dtype=np.int64)
+    y, hits = _run_int(F, x, threshold=(1 << n) // 8, cap=4096)
+    ref = O.wht_fig1(x)
+    assert np.array_equal(y, ref)
+    ridx, rval, rcnt = O.threshold(ref, (1 << n) // 8)
+    gi, gv = hits.sorted()
+    assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64, np.float32])
+def test_standalone_threshold(F, O, dtype):
+    n = 19
+    if dtype == np.float32:
+        x = synth.normal(1 << n, 3) * 4
+        T = 9.5
+    else:
+        x = synth.ints(1 << n, 3, -1000, 1000, dtype=dtype)
+        T = 990
+    x[5] = T
+    x[6] = -T
+    hits = F.threshold(_dev(x), T, cap=1 << 14)
+    ridx, rval, rcnt = O.threshold(x, T)
+    gi, gv = hits.sorted()
+    assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval.astype(dtype))
+    assert 5 not in set(gi.tolist())
+
+
+def test_repeat_runs_bit_identical(F):
+    n = 22
+    x = synth.signs(1 << n, 11)
+    outs = [_run_int(F, x)[0] for _ in range(3)]
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_involution_on_gpu(F):
+    n = 23
+    x = synth.ints(1 << n, 12, -100, 100, dtype=np.int32)
+    t = _dev(x)
+    F.fwht_int_(t)
+    F.fwht_int_(t)
+    assert np.array_equal(t.cpu().numpy(), x * (1 << n))
+
+
+def test_config_n30_planted_sampled(F, O):
+    """n = 30 planted peak (seed 2, p = 0.45, T = 6 * 2^15) in the bench's launch
+    configuration: closed-form peak, definition at sampled k, threshold set,
+    and full element-by-element parity against the multi-threaded Fig. 2."""
+    import torch
+    n, T = 30, 6 * (1 << 15)
+    x, s, err = synth.planted(n, 2, 0.45)
+    t = _dev(x)
+    hits = F.fwht_int_(t, threshold=T, cap=1 << 16)
+    y = t.cpu().numpy()
+    del t
+    torch.cuda.empty_cache()
+    assert int(y[s]) == (1 << n) - 2 * err
+    rng = np.random.default_rng(0)
+    ks = [0, s, (1 << n) - 1] + [int(k) for k in rng.integers(0, 1 << n, size=3)]
+    assert np.array_equal(O.wht_def_at(x, ks), y[ks].astype(np.int64))
+    ridx, rval, rcnt = O.threshold(y, T)
+    gi, gv = hits.sorted()
+    assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+    assert s in set(gi.tolist())
+    O.wht_fig2_inplace(x, 4)
+    assert np.array_equal(y, x)
