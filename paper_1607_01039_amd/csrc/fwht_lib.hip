@@ -41,10 +41,15 @@ int hip_fail(hipError_t e, const char *what)
 template <int TB, int CB, int NT, bool COLS, class S>
 static hipError_t launch_tile(void *buf, const PassArgs &a, hipStream_t s)
 {
+    constexpr int MINW = 2;
     const uint64_t maxgrid = 1ull << 30;
     const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
-    hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S>), dim3((uint32_t)grid), dim3(NT), 0, s,
-                       (S *)buf, a);
+    if (a.thresh)
+        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, true, MINW>), dim3((uint32_t)grid), dim3(NT), 0,
+                           s, (S *)buf, a);
+    else
+        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, false, MINW>), dim3((uint32_t)grid), dim3(NT), 0,
+                           s, (S *)buf, a);
     return hipGetLastError();
 }
 

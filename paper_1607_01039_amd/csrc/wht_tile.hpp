@@ -85,6 +85,15 @@ constexpr LayoutList make_layouts(int TB, int CB, int K, int VB, bool cols)
     return L;
 }
 
+// The lowest `k` set bits of m.
+constexpr uint32_t low_set_bits(uint32_t m, int k)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 32 && k > 0; ++b)
+        if ((m >> b) & 1u) { r |= 1u << b; --k; }
+    return r;
+}
+
 // A layout is store-friendly when its lowest non-register bits are the low
 // bits of the tile, i.e. the lanes of a wave write consecutive entries.
 constexpr bool lanes_contiguous(uint32_t m, int nlanebits)
@@ -201,7 +210,7 @@ __device__ __forceinline__ void reg_stages(S (&v)[E], uint32_t act)
 
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
-template <int TB, int CB, int NT, bool COLS, class S>
+template <int TB, int CB, int NT, bool COLS, class S, bool TH>
 struct TileKernel {
     static constexpr int E = (1 << TB) / NT;
     static constexpr int K = clog2(E);
@@ -211,21 +220,44 @@ struct TileKernel {
     static constexpr LayoutList LS = make_layouts(TB, CB, K, VB, COLS);
     static constexpr uint32_t FULL = lowmask(TB);
     static constexpr int LDS_ELEMS = (1 << TB) + (1 << TB) / 32;
+    // Lanes of a store-friendly layout write >= 256 contiguous bytes.
+    static constexpr int SLB = 8 - clog2(sizeof(S));
     static_assert(E * NT == (1 << TB), "tile must split evenly");
     static_assert(E >= VEC, "a thread must hold at least one vector");
     static_assert(K - VB <= R, "top register bits must be row bits");
     static_assert(CB >= VB + 2, "a row segment must be at least 4 vectors");
     static_assert(NT % 64 == 0, "whole waves");
     static_assert(LS.n <= 8, "too many layouts");
-    // The lanes of the store layout must write whole 64-lane runs.
-    // Lanes of a store-friendly layout write >= 256 contiguous bytes.
-    static constexpr int SLB = 8 - clog2(sizeof(S));
     static_assert(lanes_contiguous(LS.m[LS.n - 1], SLB) || LS.n == 1, "store layout");
 
-    // Global offset of tile index `idx` (row part scaled by the row stride).
-    __device__ static __forceinline__ uint64_t goff(uint64_t base, uint32_t idx, uint32_t b)
+    // Global offset (entries) of tile bits `idx`; the row stride is 2^b
+    // (2^CB for a contiguous pass, known at compile time).  The map is linear
+    // over disjoint bit sets, so lane, wave and register parts add up.
+    __device__ static __forceinline__ uint64_t goff(uint32_t idx, uint32_t b)
     {
-        return base + ((uint64_t)(idx >> CB) << b) + (idx & lowmask(CB));
+        const uint32_t bb = COLS ? (uint32_t)CB : b;
+        return ((uint64_t)(idx >> CB) << bb) + (idx & lowmask(CB));
+    }
+
+    // Per-layout split of the thread bits: lanes take the lowest six.
+    template <uint32_t M>
+    struct Split {
+        static constexpr uint32_t TM = FULL & ~M;
+        static constexpr uint32_t LANE = low_set_bits(TM, 6);
+        static constexpr uint32_t WAVE = TM & ~LANE;
+    };
+
+    // Byte offset of this lane's part (small: it spans at most 64 entries of
+    // a row and a few rows) and the wave-uniform part (entries) of a layout.
+    template <uint32_t M>
+    __device__ static __forceinline__ uint32_t lane_bytes(uint32_t lane, uint32_t b)
+    {
+        return (uint32_t)(goff(pdep_rt<Split<M>::LANE>(lane), b) * sizeof(S));
+    }
+    template <uint32_t M>
+    __device__ static __forceinline__ uint64_t wave_off(uint32_t wave, uint32_t b)
+    {
+        return goff(pdep_rt<Split<M>::WAVE>(wave), b);
     }
 
     template <int P>
@@ -250,66 +282,12 @@ struct TileKernel {
         });
     }
 
-    __device__ static void run(S *__restrict__ buf, const PassArgs &a)
+    __device__ static __forceinline__ void dispatch_to_lds(S *lds, const S (&v)[E], uint32_t t, int p)
     {
-        __shared__ S lds[LDS_ELEMS];
-        const uint32_t t = threadIdx.x;
-        for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-            const uint64_t g = tile / a.colblocks;
-            const uint64_t cb = tile - g * a.colblocks;
-            const uint64_t base = ((g << R) << a.b) + (cb << CB);
-            const bool full = (((g + 1) << R) << a.b) <= a.total;
-
-            S v[E];
-            // ---- load in layout L0: VEC consecutive entries per 16-byte access
-            {
-                constexpr uint32_t M0 = LS.m[0];
-                const uint32_t tp = pdep_rt<FULL & ~M0>(t);
-                static_for<0, E / VEC>([&](auto JT) {
-                    constexpr int jt = decltype(JT)::value;
-                    constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
-                    const uint64_t off = goff(base, jp | tp, a.b);
-                    if (full || off + VEC <= a.total) {
-                        const uint4 q = *reinterpret_cast<const uint4 *>(buf + off);
-                        const S *qs = reinterpret_cast<const S *>(&q);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e)
-                            v[jt * VEC + e] = (off + e < a.total) ? buf[off + e] : S(0);
-                    }
-                });
-            }
-            reg_stages<S, LS.m[0], LS.fresh[0], E>(v, a.act);
-
-            // ---- remaining layouts, skipping those without transformed bits
-            int cur = 0;
-            bool wrote = false;
-            static_for<1, LS.n>([&](auto PP) {
-                constexpr int P = decltype(PP)::value;
-                if (a.act & LS.fresh[P]) {
-                    if (wrote) __syncthreads();
-                    dispatch_to_lds(lds, v, t, cur);
-                    __syncthreads();
-                    from_lds<P>(lds, v, t);
-                    wrote = true;
-                    cur = P;
-                    reg_stages<S, LS.m[P], LS.fresh[P], E>(v, a.act);
-                }
-            });
-            // The store layout: L0, or any layout whose lanes are contiguous.
-            if (cur != 0 && !store_ok(cur)) {
-                if (wrote) __syncthreads();
-                dispatch_to_lds(lds, v, t, cur);
-                __syncthreads();
-                from_lds<0>(lds, v, t);
-                cur = 0;
-            }
-            if (cur == 0) store_vec(buf, v, t, base, full, a);
-            else dispatch_store(buf, v, t, base, full, a, cur);
-            __syncthreads();  // the next tile reuses the LDS buffer
-        }
+        static_for<0, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if (P == p) to_lds<P>(lds, v, t);
+        });
     }
 
     __device__ static __forceinline__ bool store_ok(int p)
@@ -322,45 +300,63 @@ struct TileKernel {
         return ok;
     }
 
-    __device__ static __forceinline__ void dispatch_to_lds(S *lds, const S (&v)[E], uint32_t t, int p)
-    {
-        static_for<0, LS.n>([&](auto PP) {
-            constexpr int P = decltype(PP)::value;
-            if (P == p) to_lds<P>(lds, v, t);
-        });
-    }
-
-    __device__ static __forceinline__ S epi(S x, const PassArgs &a)
-    {
-        if constexpr (std::is_same<S, float>::value) {
-            if (a.do_scale) x *= a.scale;
-        }
-        return x;
-    }
-
-    __device__ static __forceinline__ void store_vec(S *__restrict__ buf, S (&v)[E], uint32_t t,
-                                                     uint64_t base, bool full, const PassArgs &a)
+    template <bool FULLT>
+    __device__ static __forceinline__ void load_vec(const S *__restrict__ buf, S (&v)[E], uint32_t lane,
+                                                    uint32_t wave, uint64_t base, const PassArgs &a)
     {
         constexpr uint32_t M0 = LS.m[0];
-        const uint32_t tp = pdep_rt<FULL & ~M0>(t);
+        const uint32_t lb = lane_bytes<M0>(lane, a.b);
+        const uint64_t wb = base + wave_off<M0>(wave, a.b);
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
-            const uint64_t off = goff(base, jp | tp, a.b);
+            const S *p = buf + (wb + goff(jp, a.b));
+            if (FULLT) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(p) + lb);
+                const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = epi(v[jt * VEC + e], a);
-            if (a.thresh) {
+                for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
+            } else {
+                const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
+                if (off + VEC <= a.total) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(buf + off);
+                    const S *qs = reinterpret_cast<const S *>(&q);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = (off + e < a.total) ? buf[off + e] : S(0);
+                }
+            }
+        });
+    }
+
+    template <bool FULLT>
+    __device__ static __forceinline__ void store_vec(S *__restrict__ buf, const S (&v)[E], uint32_t lane,
+                                                     uint32_t wave, uint64_t base, const PassArgs &a)
+    {
+        constexpr uint32_t M0 = LS.m[0];
+        const uint32_t lb = lane_bytes<M0>(lane, a.b);
+        const uint64_t wb = base + wave_off<M0>(wave, a.b);
+        static_for<0, E / VEC>([&](auto JT) {
+            constexpr int jt = decltype(JT)::value;
+            constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
+            S *p = buf + (wb + goff(jp, a.b));
+            const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
+            if constexpr (TH) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const bool in = full || off + e < a.total;
+                    const bool in = FULLT || off + e < a.total;
                     emit_hits<S>(in && Arith<S>::above(v[jt * VEC + e], a), off + e, v[jt * VEC + e], a);
                 }
             }
-            if (full || off + VEC <= a.total) {
-                uint4 q;
-                S *qs = reinterpret_cast<S *>(&q);
+            uint4 q;
+            S *qs = reinterpret_cast<S *>(&q);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
+            for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
+            if (FULLT) {
+                *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(p) + lb) = q;
+            } else if (off + VEC <= a.total) {
                 *reinterpret_cast<uint4 *>(buf + off) = q;
             } else {
 #pragma unroll
@@ -370,39 +366,106 @@ struct TileKernel {
         });
     }
 
-    template <int P>
-    __device__ static __forceinline__ void store_layout(S *__restrict__ buf, S (&v)[E], uint32_t t,
-                                                        uint64_t base, bool full, const PassArgs &a)
+    template <int P, bool FULLT>
+    __device__ static __forceinline__ void store_layout(S *__restrict__ buf, const S (&v)[E], uint32_t lane,
+                                                        uint32_t wave, uint64_t base, const PassArgs &a)
     {
         constexpr uint32_t M = LS.m[P];
-        const uint32_t tp = pdep_rt<FULL & ~M>(t);
+        const uint32_t lb = lane_bytes<M>(lane, a.b);
+        const uint64_t wb = base + wave_off<M>(wave, a.b);
         static_for<0, E>([&](auto J) {
             constexpr int j = decltype(J)::value;
             constexpr uint32_t jp = cpdep((uint32_t)j, M);
-            const uint64_t off = goff(base, jp | tp, a.b);
-            const S x = epi(v[j], a);
-            const bool in = full || off < a.total;
-            if (a.thresh) emit_hits<S>(in && Arith<S>::above(x, a), off, x, a);
-            if (in) buf[off] = x;
+            S *p = buf + (wb + goff(jp, a.b));
+            if (FULLT) {
+                if constexpr (TH)
+                    emit_hits<S>(Arith<S>::above(v[j], a), (uint64_t)(p - buf) + lb / sizeof(S), v[j], a);
+                *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb) = v[j];
+            } else {
+                const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
+                const bool in = off < a.total;
+                if constexpr (TH) emit_hits<S>(in && Arith<S>::above(v[j], a), off, v[j], a);
+                if (in) buf[off] = v[j];
+            }
         });
     }
 
-    __device__ static __forceinline__ void dispatch_store(S *__restrict__ buf, S (&v)[E], uint32_t t,
-                                                          uint64_t base, bool full, const PassArgs &a, int p)
+    template <bool FULLT>
+    __device__ static __forceinline__ void dispatch_store(S *__restrict__ buf, const S (&v)[E], uint32_t lane,
+                                                          uint32_t wave, uint64_t base, const PassArgs &a, int p)
     {
         static_for<1, LS.n>([&](auto PP) {
             constexpr int P = decltype(PP)::value;
             if constexpr (lanes_contiguous(LS.m[P], SLB)) {
-                if (P == p) store_layout<P>(buf, v, t, base, full, a);
+                if (P == p) store_layout<P, FULLT>(buf, v, lane, wave, base, a);
             }
         });
     }
+
+    template <bool FULLT>
+    __device__ static __forceinline__ void tile_body(S *__restrict__ buf, S *lds, uint32_t t, uint64_t base,
+                                                     const PassArgs &a)
+    {
+        const uint32_t lane = t & 63u;
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+        S v[E];
+        load_vec<FULLT>(buf, v, lane, wave, base, a);
+        reg_stages<S, LS.m[0], LS.fresh[0], E>(v, a.act);
+        // remaining layouts, skipping those that own no transformed bit
+        int cur = 0;
+        bool wrote = false;
+        static_for<1, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if (a.act & LS.fresh[P]) {
+                if (wrote) __syncthreads();
+                dispatch_to_lds(lds, v, t, cur);
+                __syncthreads();
+                from_lds<P>(lds, v, t);
+                wrote = true;
+                cur = P;
+                reg_stages<S, LS.m[P], LS.fresh[P], E>(v, a.act);
+            }
+        });
+        if (cur != 0 && !store_ok(cur)) {
+            __syncthreads();
+            dispatch_to_lds(lds, v, t, cur);
+            __syncthreads();
+            from_lds<0>(lds, v, t);
+            cur = 0;
+        }
+        if constexpr (std::is_same<S, float>::value) {
+            if (a.do_scale) {
+#pragma unroll
+                for (int j = 0; j < E; ++j) v[j] *= a.scale;
+            }
+        }
+        if (cur == 0) store_vec<FULLT>(buf, v, lane, wave, base, a);
+        else dispatch_store<FULLT>(buf, v, lane, wave, base, a, cur);
+        if (wrote) __syncthreads();  // the next tile reuses the LDS buffer
+    }
+
+    __device__ static __forceinline__ void run(S *__restrict__ buf, const PassArgs &a)
+    {
+        __shared__ S lds[LDS_ELEMS];
+        const uint32_t t = threadIdx.x;
+        const uint32_t b = COLS ? (uint32_t)CB : a.b;
+        for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+            const uint64_t g = tile / a.colblocks;
+            const uint64_t cb = tile - g * a.colblocks;
+            const uint64_t base = ((g << R) << b) + (cb << CB);
+            if ((((g + 1) << R) << b) <= a.total) tile_body<true>(buf, lds, t, base, a);
+            else tile_body<false>(buf, lds, t, base, a);
+        }
+    }
 };
 
-template <int TB, int CB, int NT, bool COLS, class S>
-__global__ void __launch_bounds__(NT) wht_tile_kernel(S *__restrict__ buf, PassArgs a)
+// Each variant is compiled to keep at least MINW waves per SIMD resident
+// (register budget 512 / MINW), so that several tiles share a CU and one
+// tile's LDS phases overlap another tile's HBM traffic.
+template <int TB, int CB, int NT, bool COLS, class S, bool TH, int MINW>
+__global__ void __launch_bounds__(NT, MINW) wht_tile_kernel(S *__restrict__ buf, PassArgs a)
 {
-    TileKernel<TB, CB, NT, COLS, S>::run(buf, a);
+    TileKernel<TB, CB, NT, COLS, S, TH>::run(buf, a);
 }
 
 }  // namespace fwht
