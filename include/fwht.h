@@ -135,6 +135,12 @@ int fwht_norms(const float *x, const float *y, const double *r, const int64_t *o
  * variant or a schedule that does not cover n bits. */
 int fwht_set_schedule(int dtype, int n, const char *spec);
 
+/* Writes the names of the compiled pass variants for `dtype`, comma-separated
+ * ("C<TB>": contiguous pass over tiles of 2^TB entries; "S<TB>c<CB>": strided
+ * pass over tiles of 2^(TB-CB) rows x 2^CB contiguous entries), NUL-terminated
+ * and truncated to len. */
+int fwht_list_variants(int dtype, char *buf, int len);
+
 /* Writes the schedule fwht_int / fwht_float would use for (dtype, n) into
  * buf (NUL-terminated, truncated to len). */
 int fwht_get_schedule(int dtype, int n, char *buf, int len);

@@ -204,6 +204,14 @@ def set_schedule(dtype: str, n: int, spec):
     _lib.check(_lib.lib().fwht_set_schedule(dt, n, spec.encode() if spec else None))
 
 
+def list_variants(dtype: str):
+    """Names of the compiled pass variants for `dtype`."""
+    dt = {"int32": _lib.FWHT_I32, "int64": _lib.FWHT_I64, "float32": _lib.FWHT_F32}[dtype]
+    buf = C.create_string_buffer(4096)
+    _lib.check(_lib.lib().fwht_list_variants(dt, buf, 4096))
+    return buf.value.decode().split(",")
+
+
 def get_schedule(dtype: str, n: int) -> str:
     dt = {"int32": _lib.FWHT_I32, "int64": _lib.FWHT_I64, "float32": _lib.FWHT_F32}[dtype]
     buf = C.create_string_buffer(256)

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "FWHT_OK", 1: "FWHT_E_INVAL", 2: "FWHT_E_RANGE", 3: "FWHT_E_C
 
 # Every symbol include/fwht.h declares.
 EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
-           "fwht_set_schedule", "fwht_get_schedule", "fwht_trace_enable", "fwht_trace_read",
+           "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_trace_enable", "fwht_trace_read",
            "fwht_copy", "fwht_last_error", "fwht_version")
 
 
@@ -46,6 +46,10 @@ def lib() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes libfwht.so bind to that one, so both share one runtime
+    # (one device context, torch's streams valid in the library).
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64
     L.fwht_int.argtypes = [vp, i32, i32, C.POINTER(fwht_thresh_t), vp]
@@ -55,13 +59,15 @@ def lib() -> C.CDLL:
     L.fwht_norms.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     L.fwht_set_schedule.argtypes = [i32, i32, C.c_char_p]
     L.fwht_get_schedule.argtypes = [i32, i32, C.c_char_p, i32]
+    L.fwht_list_variants.argtypes = [i32, C.c_char_p, i32]
     L.fwht_copy.argtypes = [vp, vp, u64, vp]
     L.fwht_trace_enable.argtypes = [i32]
     L.fwht_trace_read.argtypes = [vp, i32, C.POINTER(C.c_int), C.c_char_p, i32]
     L.fwht_last_error.restype = C.c_char_p
     L.fwht_version.restype = C.c_char_p
     for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
-                 "fwht_set_schedule", "fwht_get_schedule", "fwht_copy", "fwht_trace_enable",
+                 "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_copy",
+                 "fwht_trace_enable",
                  "fwht_trace_read"):
         getattr(L, name).restype = C.c_int
     _lib = L

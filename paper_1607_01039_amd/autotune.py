@@ -1,0 +1,169 @@
+"""Autotuner for the pass schedule of fwht_int / fwht_float on the local GPU.
+
+For each (dtype, n) it times every schedule with the minimum number of HBM
+passes: a contiguous pass of c bits followed by strided passes whose bit
+counts and row-segment widths (2^cb entries) vary, each strided pass using the
+variant whose tile height equals its bit count.  The fastest schedule per
+(dtype, n) is written to tune/gfx950.txt, which libfwht.so reads at start-up.
+
+    python -m paper_1607_01039_amd.autotune --dtype int32 --n 16-30
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import os
+import sys
+import time
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(PKG, "tune", "gfx950.txt")
+
+# Compiled variants (must match csrc/fwht_variants_*.hip).
+CONTIG = {"int32": (12, 13, 14, 15), "float32": (12, 13, 14, 15), "int64": (11, 12, 13, 14)}
+SEGMENT_BITS = {"int32": (5, 6, 7), "float32": (5, 6, 7), "int64": (4, 5, 6)}
+MAX_TILE_BYTES = 128 * 1024
+RMAX = 9
+
+
+def strided_variant(dtype: str, r: int, cb: int):
+    esz = 8 if dtype == "int64" else 4
+    tb = cb + r
+    if (1 << tb) * esz > MAX_TILE_BYTES:
+        return None
+    vec = 16 // esz
+    nt = (1 << tb) // 32 if tb >= 14 else max(64, (1 << tb) // 16)
+    if (1 << tb) // nt < vec:
+        return None
+    return f"S{tb}c{cb}"
+
+
+def compositions(s: int, k: int, lo: int = 1, hi: int = RMAX):
+    if k == 1:
+        if lo <= s <= hi:
+            yield (s,)
+        return
+    for first in range(lo, hi + 1):
+        for rest in compositions(s - first, k - 1, lo, hi):
+            yield (first,) + rest
+
+
+def candidates(dtype: str, n: int, max_cands: int = 400):
+    cmax = max(CONTIG[dtype])
+    if n <= cmax:
+        return [f"C{max(min(CONTIG[dtype]), n)}"]
+    best_p = min(1 + -(-(n - c) // RMAX) for c in CONTIG[dtype] if c <= n)
+    out = []
+    for c in CONTIG[dtype]:
+        s = n - c
+        ns = best_p - 1
+        if ns < 1 or s > ns * RMAX or s < ns:
+            continue
+        for comp in compositions(s, ns, 2 if s >= 2 * ns else 1):
+            if max(comp) - min(comp) > 2:
+                continue
+            for cbs in itertools.product(SEGMENT_BITS[dtype], repeat=ns):
+                parts = [strided_variant(dtype, r, cb) for r, cb in zip(comp, cbs)]
+                if None in parts:
+                    continue
+                out.append(",".join([f"C{c}"] + [f"{v}:{r}" for v, r in zip(parts, comp)]))
+    return out[:max_cands]
+
+
+def time_schedule(F, torch, buf, dtype, n, spec, reps=5):
+    F.set_schedule(dtype, n, spec)
+    run = (lambda: F.fwht_float_(buf)) if dtype == "float32" else (lambda: F.fwht_int_(buf))
+    run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def tune(dtype: str, ns, min_total_bits: int = 0, log=print):
+    import torch
+
+    import paper_1607_01039_amd as F
+    tdt = {"int32": torch.int32, "int64": torch.int64, "float32": torch.float32}[dtype]
+    results = {}
+    for n in ns:
+        total_bits = max(n, min_total_bits) if dtype == "float32" else n
+        if dtype == "float32":
+            buf = torch.randn((1 << (total_bits - n), 1 << n), device="cuda", dtype=tdt)
+        else:
+            buf = torch.randint(-1, 2, (1 << n,), device="cuda", dtype=tdt)
+        F.set_schedule(dtype, n, None)
+        default = F.get_schedule(dtype, n)
+        cands = candidates(dtype, n)
+        if default not in cands:
+            cands.append(default)
+        best = None
+        t0 = time.time()
+        for spec in cands:
+            ms = time_schedule(F, torch, buf, dtype, n, spec)
+            if best is None or ms < best[1]:
+                best = (spec, ms)
+        F.set_schedule(dtype, n, None)
+        ms_def = time_schedule(F, torch, buf, dtype, n, default) if len(cands) > 1 else best[1]
+        F.set_schedule(dtype, n, None)
+        results[n] = best
+        log(f"[tune] {dtype} n={n} total=2^{total_bits}: {len(cands)} schedules in {time.time() - t0:.1f}s; "
+            f"best {best[0]} {best[1]:.4f} ms (default {default} {ms_def:.4f} ms)")
+        del buf
+        torch.cuda.empty_cache()
+    return results
+
+
+def write_table(path: str, updates: dict):
+    """Merge {(dtype, n): (spec, ms)} into the table file."""
+    rows = {}
+    if os.path.exists(path):
+        for line in open(path):
+            line = line.split("#")[0].split()
+            if len(line) >= 3:
+                rows[(line[0], int(line[1]))] = (line[2], float(line[3]) if len(line) > 3 else float("nan"))
+    rows.update(updates)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        f.write("# dtype n schedule ms  -- written by paper_1607_01039_amd/autotune.py on MI355X (gfx950)\n")
+        for (dt, n) in sorted(rows, key=lambda k: (k[0], k[1])):
+            spec, ms = rows[(dt, n)]
+            f.write(f"{dt} {n} {spec} {ms:.4f}\n")
+
+
+def parse_range(s: str):
+    out = []
+    for part in s.split(","):
+        if "-" in part:
+            a, b = part.split("-")
+            out.extend(range(int(a), int(b) + 1))
+        else:
+            out.append(int(part))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dtype", default="int32", choices=["int32", "int64", "float32"])
+    ap.add_argument("--n", default="16-30")
+    ap.add_argument("--float-total-bits", type=int, default=28,
+                    help="float32: batch so that batch * 2^n = 2^this (the transform size stays 2^n)")
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args()
+    res = tune(args.dtype, parse_range(args.n), args.float_total_bits,
+               log=lambda m: print(m, flush=True))
+    write_table(args.out, {(args.dtype, n): v for n, v in res.items()})
+    print(f"wrote {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(PKG))
+    main()

@@ -44,6 +44,9 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 
 const std::vector<Variant> &registry(int dtype);
+std::vector<Variant> variants_u32();
+std::vector<Variant> variants_u64();
+std::vector<Variant> variants_f32();
 bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass> &out, std::string &why);
 std::string schedule_for(int dtype, int n);
 const std::string *tuned_schedule(int dtype, int n);

@@ -38,61 +38,13 @@ int hip_fail(hipError_t e, const char *what)
 }
 
 // ---------------------------------------------------------- kernel registry
-template <int TB, int CB, int NT, bool COLS, class S>
-static hipError_t launch_tile(void *buf, const PassArgs &a, hipStream_t s)
-{
-    constexpr int MINW = 2;
-    const uint64_t maxgrid = 1ull << 30;
-    const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
-    if (a.thresh)
-        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, true, MINW>), dim3((uint32_t)grid), dim3(NT), 0,
-                           s, (S *)buf, a);
-    else
-        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, false, MINW>), dim3((uint32_t)grid), dim3(NT), 0,
-                           s, (S *)buf, a);
-    return hipGetLastError();
-}
-
-template <class S>
-static std::vector<Variant> variants_for();
-
-#define V_CONTIG(TB, NT, S) Variant{"C" #TB, TB, 6, NT, true, &launch_tile<TB, 6, NT, true, S>}
-#define V_STRIDE(TB, CB, NT, S) Variant{"S" #TB "c" #CB, TB, CB, NT, false, &launch_tile<TB, CB, NT, false, S>}
-
-template <>
-std::vector<Variant> variants_for<uint32_t>()
-{
-    return {V_CONTIG(12, 256, uint32_t), V_CONTIG(13, 512, uint32_t), V_CONTIG(14, 512, uint32_t),
-            V_CONTIG(15, 1024, uint32_t),
-            V_STRIDE(12, 5, 256, uint32_t), V_STRIDE(13, 5, 512, uint32_t), V_STRIDE(13, 6, 512, uint32_t),
-            V_STRIDE(14, 5, 512, uint32_t), V_STRIDE(14, 6, 512, uint32_t), V_STRIDE(15, 6, 1024, uint32_t)};
-}
-template <>
-std::vector<Variant> variants_for<float>()
-{
-    return {V_CONTIG(12, 256, float), V_CONTIG(13, 512, float), V_CONTIG(14, 512, float),
-            V_CONTIG(15, 1024, float),
-            V_STRIDE(12, 5, 256, float), V_STRIDE(13, 5, 512, float), V_STRIDE(13, 6, 512, float),
-            V_STRIDE(14, 5, 512, float), V_STRIDE(14, 6, 512, float), V_STRIDE(15, 6, 1024, float)};
-}
-#undef V_CONTIG
-#define V_CONTIG(TB, NT, S) Variant{"C" #TB, TB, 5, NT, true, &launch_tile<TB, 5, NT, true, S>}
-template <>
-std::vector<Variant> variants_for<uint64_t>()
-{
-    return {V_CONTIG(11, 128, uint64_t), V_CONTIG(12, 256, uint64_t), V_CONTIG(13, 512, uint64_t),
-            V_CONTIG(14, 1024, uint64_t),
-            V_STRIDE(12, 4, 256, uint64_t), V_STRIDE(13, 4, 512, uint64_t), V_STRIDE(13, 5, 512, uint64_t),
-            V_STRIDE(14, 4, 1024, uint64_t), V_STRIDE(14, 5, 1024, uint64_t)};
-}
-#undef V_CONTIG
-#undef V_STRIDE
-
+// The variants of each element type are compiled in their own translation
+// unit (fwht_variants_*.hip).
 const std::vector<Variant> &registry(int dtype)
 {
-    static const std::vector<Variant> r32 = variants_for<uint32_t>();
-    static const std::vector<Variant> r64 = variants_for<uint64_t>();
-    static const std::vector<Variant> rf = variants_for<float>();
+    static const std::vector<Variant> r32 = variants_u32();
+    static const std::vector<Variant> r64 = variants_u64();
+    static const std::vector<Variant> rf = variants_f32();
     return dtype == FWHT_I32 ? r32 : dtype == FWHT_I64 ? r64 : rf;
 }
 
@@ -141,27 +93,34 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
     return true;
 }
 
-// Default schedules, measured on MI355X by the autotuner (tune/gfx950.txt).
+// Default schedule: the table written by the autotuner (tune/gfx950.txt next
+// to the library, or $FWHT_TUNE_TABLE) when it has (dtype, n); otherwise the
+// fewest passes: one contiguous pass of up to 2^15 (int64: 2^13) entries,
+// then strided passes of at most 9 bits, balanced, each with a variant whose
+// tile height equals its bit count and whose rows are 256-byte segments.
 std::string default_schedule(int dtype, int n)
 {
     const std::string *tuned = tuned_schedule(dtype, n);
     if (tuned) return *tuned;
-    // Heuristic: one contiguous pass of up to 14 (int64: 13) bits, then
-    // strided passes of 8 bits with 256-byte row segments, balanced.
     const bool wide = dtype == FWHT_I64;
-    const int ctb = wide ? 13 : 14;
-    if (n <= 12) return wide ? "C12" : "C12";
-    if (n <= ctb) return wide ? "C13" : (n <= 13 ? "C13" : "C14");
-    const int rest = n - ctb;
-    const int R = 8;
-    const int np = (rest + R - 1) / R;
-    std::string s = wide ? "C13" : "C14";
-    for (int i = 0; i < np; ++i) {
-        int r = rest / np + (i < rest % np ? 1 : 0);
-        s += wide ? ",S13c5:" : ",S14c6:";
-        s += std::to_string(r);
+    const int cmax = wide ? 13 : 15;
+    const int rmax = 9;
+    const int cb = wide ? 5 : 6;
+    if (n <= 12) return wide && n <= 11 ? "C11" : "C12";
+    if (n <= cmax) return "C" + std::to_string(n);
+    int P = 1;
+    while (cmax + rmax * (P - 1) < n) ++P;
+    const int ns = P - 1;
+    // Keep every strided pass at >= 3 bits (very short tiles waste lanes).
+    int c = cmax;
+    if (n - c < 3 * ns) c = n - 3 * ns;
+    const int s = n - c;
+    std::string out = "C" + std::to_string(c);
+    for (int i = 0; i < ns; ++i) {
+        const int r = s / ns + (i < s % ns ? 1 : 0);
+        out += ",S" + std::to_string(cb + r) + "c" + std::to_string(cb) + ":" + std::to_string(r);
     }
-    return s;
+    return out;
 }
 
 std::string schedule_for(int dtype, int n)
@@ -440,6 +399,19 @@ int fwht_set_schedule(int dtype, int n, const char *spec)
     std::string why;
     if (!parse_schedule(dtype, n, spec, p, why)) return fail(FWHT_E_INVAL, "schedule '%s': %s", spec, why.c_str());
     g_sched_override[{dtype, n}] = spec;
+    return FWHT_OK;
+}
+
+int fwht_list_variants(int dtype, char *buf, int len)
+{
+    if (!buf || len < 1) return fail(FWHT_E_INVAL, "bad buffer");
+    if (dtype != FWHT_I32 && dtype != FWHT_I64 && dtype != FWHT_F32) return fail(FWHT_E_INVAL, "bad dtype");
+    std::string all;
+    for (const Variant &v : registry(dtype)) {
+        if (!all.empty()) all += ",";
+        all += v.name;
+    }
+    snprintf(buf, (size_t)len, "%s", all.c_str());
     return FWHT_OK;
 }
 

@@ -1,7 +1,6 @@
 // Temporary: entry points not built yet.
 #include "fwht_internal.hpp"
 namespace fwht {
-const std::string *tuned_schedule(int, int) { return nullptr; }
 int streamed_int(void *, int, int, const fwht_thresh_t *, hipStream_t) { return fail(FWHT_E_UNSUPPORTED, "streamed path not built"); }
 int mfma_uniform(float *, int, uint64_t, int, int, hipStream_t) { return fail(FWHT_E_UNSUPPORTED, "mfma path not built"); }
 }

@@ -1,0 +1,44 @@
+// Tile-kernel variants for float32 entries (see wht_tile.hpp).
+// Name: C<TB> = contiguous pass over tiles of 2^TB entries; S<TB>c<CB> =
+// strided pass over tiles of 2^(TB-CB) rows x 2^CB contiguous columns, so it
+// transforms up to TB-CB index bits per pass.
+#include "fwht_internal.hpp"
+#include "wht_tile.hpp"
+
+namespace fwht {
+
+std::vector<Variant> variants_f32()
+{
+    using S = float;
+    return {
+        Variant{"C12", 12, 6, 256, true, &launch_tile<12, 6, 256, true, S, false>},
+        Variant{"C13", 13, 6, 512, true, &launch_tile<13, 6, 512, true, S, false>},
+        Variant{"C14", 14, 6, 512, true, &launch_tile<14, 6, 512, true, S, false>},
+        Variant{"C15", 15, 6, 1024, true, &launch_tile<15, 6, 1024, true, S, false>},
+        Variant{"S8c5", 8, 5, 64, false, &launch_tile<8, 5, 64, false, S, false>},
+        Variant{"S9c5", 9, 5, 64, false, &launch_tile<9, 5, 64, false, S, false>},
+        Variant{"S10c5", 10, 5, 64, false, &launch_tile<10, 5, 64, false, S, false>},
+        Variant{"S11c5", 11, 5, 128, false, &launch_tile<11, 5, 128, false, S, false>},
+        Variant{"S12c5", 12, 5, 256, false, &launch_tile<12, 5, 256, false, S, false>},
+        Variant{"S13c5", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, false>},
+        Variant{"S14c5", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, false>},
+        Variant{"S8c6", 8, 6, 64, false, &launch_tile<8, 6, 64, false, S, false>},
+        Variant{"S9c6", 9, 6, 64, false, &launch_tile<9, 6, 64, false, S, false>},
+        Variant{"S10c6", 10, 6, 64, false, &launch_tile<10, 6, 64, false, S, false>},
+        Variant{"S11c6", 11, 6, 128, false, &launch_tile<11, 6, 128, false, S, false>},
+        Variant{"S12c6", 12, 6, 256, false, &launch_tile<12, 6, 256, false, S, false>},
+        Variant{"S13c6", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, false>},
+        Variant{"S14c6", 14, 6, 512, false, &launch_tile<14, 6, 512, false, S, false>},
+        Variant{"S15c6", 15, 6, 1024, false, &launch_tile<15, 6, 1024, false, S, false>},
+        Variant{"S8c7", 8, 7, 64, false, &launch_tile<8, 7, 64, false, S, false>},
+        Variant{"S9c7", 9, 7, 64, false, &launch_tile<9, 7, 64, false, S, false>},
+        Variant{"S10c7", 10, 7, 64, false, &launch_tile<10, 7, 64, false, S, false>},
+        Variant{"S11c7", 11, 7, 128, false, &launch_tile<11, 7, 128, false, S, false>},
+        Variant{"S12c7", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, false>},
+        Variant{"S13c7", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, false>},
+        Variant{"S14c7", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, false>},
+        Variant{"S15c7", 15, 7, 1024, false, &launch_tile<15, 7, 1024, false, S, false>},
+    };
+}
+
+}  // namespace fwht

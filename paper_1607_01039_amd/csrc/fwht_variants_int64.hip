@@ -1,0 +1,44 @@
+// Tile-kernel variants for int64 entries (see wht_tile.hpp).
+// Name: C<TB> = contiguous pass over tiles of 2^TB entries; S<TB>c<CB> =
+// strided pass over tiles of 2^(TB-CB) rows x 2^CB contiguous columns, so it
+// transforms up to TB-CB index bits per pass.
+#include "fwht_internal.hpp"
+#include "wht_tile.hpp"
+
+namespace fwht {
+
+std::vector<Variant> variants_u64()
+{
+    using S = uint64_t;
+    return {
+        Variant{"C11", 11, 5, 128, true, &launch_tile<11, 5, 128, true, S, false>},
+        Variant{"C12", 12, 5, 256, true, &launch_tile<12, 5, 256, true, S, false>},
+        Variant{"C13", 13, 5, 512, true, &launch_tile<13, 5, 512, true, S, false>},
+        Variant{"C14", 14, 5, 512, true, &launch_tile<14, 5, 512, true, S, false>},
+        Variant{"S7c4", 7, 4, 64, false, &launch_tile<7, 4, 64, false, S, false>},
+        Variant{"S8c4", 8, 4, 64, false, &launch_tile<8, 4, 64, false, S, false>},
+        Variant{"S9c4", 9, 4, 64, false, &launch_tile<9, 4, 64, false, S, false>},
+        Variant{"S10c4", 10, 4, 64, false, &launch_tile<10, 4, 64, false, S, false>},
+        Variant{"S11c4", 11, 4, 128, false, &launch_tile<11, 4, 128, false, S, false>},
+        Variant{"S12c4", 12, 4, 256, false, &launch_tile<12, 4, 256, false, S, false>},
+        Variant{"S13c4", 13, 4, 512, false, &launch_tile<13, 4, 512, false, S, false>},
+        Variant{"S7c5", 7, 5, 64, false, &launch_tile<7, 5, 64, false, S, false>},
+        Variant{"S8c5", 8, 5, 64, false, &launch_tile<8, 5, 64, false, S, false>},
+        Variant{"S9c5", 9, 5, 64, false, &launch_tile<9, 5, 64, false, S, false>},
+        Variant{"S10c5", 10, 5, 64, false, &launch_tile<10, 5, 64, false, S, false>},
+        Variant{"S11c5", 11, 5, 128, false, &launch_tile<11, 5, 128, false, S, false>},
+        Variant{"S12c5", 12, 5, 256, false, &launch_tile<12, 5, 256, false, S, false>},
+        Variant{"S13c5", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, false>},
+        Variant{"S14c5", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, false>},
+        Variant{"S7c6", 7, 6, 64, false, &launch_tile<7, 6, 64, false, S, false>},
+        Variant{"S8c6", 8, 6, 64, false, &launch_tile<8, 6, 64, false, S, false>},
+        Variant{"S9c6", 9, 6, 64, false, &launch_tile<9, 6, 64, false, S, false>},
+        Variant{"S10c6", 10, 6, 64, false, &launch_tile<10, 6, 64, false, S, false>},
+        Variant{"S11c6", 11, 6, 128, false, &launch_tile<11, 6, 128, false, S, false>},
+        Variant{"S12c6", 12, 6, 256, false, &launch_tile<12, 6, 256, false, S, false>},
+        Variant{"S13c6", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, false>},
+        Variant{"S14c6", 14, 6, 512, false, &launch_tile<14, 6, 512, false, S, false>},
+    };
+}
+
+}  // namespace fwht

@@ -210,7 +210,30 @@ __device__ __forceinline__ void reg_stages(S (&v)[E], uint32_t act)
 
 __device__ __forceinline__ uint32_t lds_pad(uint32_t i) { return i + (i >> 5); }
 
-template <int TB, int CB, int NT, bool COLS, class S, bool TH>
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// 16-byte global load / store; NT marks the access non-temporal (the data is
+// streamed once per pass and will not be re-read before eviction).
+template <bool NT>
+__device__ __forceinline__ v4u gload16(const void *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+    else return *reinterpret_cast<const v4u *>(p);
+}
+template <bool NT>
+__device__ __forceinline__ void gstore16(void *p, v4u q)
+{
+    if constexpr (NT) __builtin_nontemporal_store(q, reinterpret_cast<v4u *>(p));
+    else *reinterpret_cast<v4u *>(p) = q;
+}
+template <bool NT, class S>
+__device__ __forceinline__ void gstore1(S *p, S x)
+{
+    if constexpr (NT) __builtin_nontemporal_store(x, p);
+    else *p = x;
+}
+
+template <int TB, int CB, int NT, bool COLS, class S, bool TH, bool NTM>
 struct TileKernel {
     static constexpr int E = (1 << TB) / NT;
     static constexpr int K = clog2(E);
@@ -220,8 +243,9 @@ struct TileKernel {
     static constexpr LayoutList LS = make_layouts(TB, CB, K, VB, COLS);
     static constexpr uint32_t FULL = lowmask(TB);
     static constexpr int LDS_ELEMS = (1 << TB) + (1 << TB) / 32;
-    // Lanes of a store-friendly layout write >= 256 contiguous bytes.
-    static constexpr int SLB = 8 - clog2(sizeof(S));
+    // Lanes of a store-friendly layout write >= 256 contiguous bytes, or a
+    // whole row segment when segments are shorter.
+    static constexpr int SLB = (8 - clog2(sizeof(S))) < CB ? (8 - clog2(sizeof(S))) : CB;
     static_assert(E * NT == (1 << TB), "tile must split evenly");
     static_assert(E >= VEC, "a thread must hold at least one vector");
     static_assert(K - VB <= R, "top register bits must be row bits");
@@ -312,14 +336,14 @@ struct TileKernel {
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
             const S *p = buf + (wb + goff(jp, a.b));
             if (FULLT) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(p) + lb);
+                const v4u q = gload16<NTM>(reinterpret_cast<const char *>(p) + lb);
                 const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
             } else {
                 const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
                 if (off + VEC <= a.total) {
-                    const uint4 q = *reinterpret_cast<const uint4 *>(buf + off);
+                    const v4u q = gload16<NTM>(buf + off);
                     const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -350,14 +374,14 @@ struct TileKernel {
                     emit_hits<S>(in && Arith<S>::above(v[jt * VEC + e], a), off + e, v[jt * VEC + e], a);
                 }
             }
-            uint4 q;
+            v4u q;
             S *qs = reinterpret_cast<S *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
             if (FULLT) {
-                *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(p) + lb) = q;
+                gstore16<NTM>(reinterpret_cast<char *>(p) + lb, q);
             } else if (off + VEC <= a.total) {
-                *reinterpret_cast<uint4 *>(buf + off) = q;
+                gstore16<NTM>(buf + off, q);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -380,7 +404,7 @@ struct TileKernel {
             if (FULLT) {
                 if constexpr (TH)
                     emit_hits<S>(Arith<S>::above(v[j], a), (uint64_t)(p - buf) + lb / sizeof(S), v[j], a);
-                *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb) = v[j];
+                gstore1<NTM>(reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb), v[j]);
             } else {
                 const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
                 const bool in = off < a.total;
@@ -462,10 +486,26 @@ struct TileKernel {
 // Each variant is compiled to keep at least MINW waves per SIMD resident
 // (register budget 512 / MINW), so that several tiles share a CU and one
 // tile's LDS phases overlap another tile's HBM traffic.
-template <int TB, int CB, int NT, bool COLS, class S, bool TH, int MINW>
+template <int TB, int CB, int NT, bool COLS, class S, bool TH, bool NTM, int MINW>
 __global__ void __launch_bounds__(NT, MINW) wht_tile_kernel(S *__restrict__ buf, PassArgs a)
 {
-    TileKernel<TB, CB, NT, COLS, S, TH>::run(buf, a);
+    TileKernel<TB, CB, NT, COLS, S, TH, NTM>::run(buf, a);
+}
+
+// Host-side launcher of one variant (threshold epilogue chosen per launch).
+template <int TB, int CB, int NT, bool COLS, class S, bool NTM>
+hipError_t launch_tile(void *buf, const PassArgs &a, hipStream_t s)
+{
+    constexpr int MINW = 2;
+    const uint64_t maxgrid = 1ull << 30;
+    const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
+    if (a.thresh)
+        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, true, NTM, MINW>), dim3((uint32_t)grid), dim3(NT),
+                           0, s, (S *)buf, a);
+    else
+        hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, false, NTM, MINW>), dim3((uint32_t)grid), dim3(NT),
+                           0, s, (S *)buf, a);
+    return hipGetLastError();
 }
 
 }  // namespace fwht

@@ -70,3 +70,32 @@ def test_float_integer_inputs_exact(F, O):
     t = _dev(x)
     F.fwht_float_(t, normalize=False)
     assert np.array_equal(t.cpu().numpy().astype(np.float64), O.wht_fig1(x))
+
+
+def _float_variant_cases():
+    import paper_1607_01039_amd as F
+    try:
+        vs = F.list_variants("float32")
+    except Exception:
+        return [("unbuilt", 0, "")]
+    cases = []
+    for v in vs:
+        if v.startswith("C"):
+            cases.append((v, int(v[1:]), v))
+        else:
+            tb, cb = (int(x) for x in v[1:].split("c"))
+            cases.append((v, 12 + tb - cb, f"C12,{v}:{tb - cb}"))
+    return cases
+
+
+@pytest.mark.parametrize("variant,n,spec", _float_variant_cases())
+def test_every_variant_float(F, O, variant, n, spec):
+    x = synth.normal((2, 1 << n), 60 + n)
+    F.set_schedule("float32", n, spec)
+    try:
+        t = _dev(x)
+        F.fwht_float_(t, normalize=True)
+        y = t.cpu().numpy()
+    finally:
+        F.set_schedule("float32", n, None)
+    assert normwise(y, O.wht_batch(x, n, True)) <= tol(n)

@@ -65,8 +65,56 @@ SCHEDULES_I32 = {
     26: ["C12,S14c6,S14c6:6", "C15,S15c6:9,S12c5:2", "C14,S13c6:6,S13c6:6"],
 }
 SCHEDULES_I64 = {
-    20: ["C11,S12c4:8,S13c5:1", "C14:6,S14c5,S12c4:5", "C13,S14c4:7"],
+    20: ["C11,S12c4:8,S13c5:1", "C14:6,S14c5,S12c4:5", "C13,S13c6:7"],
 }
+
+
+def _variant_cases(dtype):
+    """(variant, n, spec): every compiled variant once as the only pass of
+    its kind at its full height, and strided ones also at a partial height."""
+    import paper_1607_01039_amd as F
+    cases = []
+    for v in F.list_variants(dtype):
+        if v.startswith("C"):
+            tb = int(v[1:])
+            cases.append((v, tb, v))
+            cases.append((v, tb - 3, v))
+        else:
+            tb, cb = (int(x) for x in v[1:].split("c"))
+            R = tb - cb
+            cases.append((v, 12 + R, f"C12,{v}:{R}"))
+            if R > 1:
+                cases.append((v, 12 + R - 1, f"C12,{v}:{R - 1}"))
+    return cases
+
+
+def _cases_or_empty(dtype):
+    try:
+        return _variant_cases(dtype)
+    except Exception:  # library not built: the test itself will fail loudly
+        return [("unbuilt", 0, "")]
+
+
+@pytest.mark.parametrize("variant,n,spec", _cases_or_empty("int32"))
+def test_every_variant_int32(F, O, variant, n, spec):
+    x = synth.ints(1 << n, 40 + n, -(1 << 20), 1 << 20, dtype=np.int32)
+    F.set_schedule("int32", n, spec)
+    try:
+        y, _ = _run_int(F, x)
+    finally:
+        F.set_schedule("int32", n, None)
+    assert np.array_equal(y, O.wht_fig1(x))
+
+
+@pytest.mark.parametrize("variant,n,spec", _cases_or_empty("int64"))
+def test_every_variant_int64(F, O, variant, n, spec):
+    x = synth.ints(1 << n, 50 + n, -(1 << 40), 1 << 40, dtype=np.int64)
+    F.set_schedule("int64", n, spec)
+    try:
+        y, _ = _run_int(F, x)
+    finally:
+        F.set_schedule("int64", n, None)
+    assert np.array_equal(y, O.wht_fig1(x))
 
 
 @pytest.mark.parametrize("n,spec", [(n, s) for n, ss in SCHEDULES_I32.items() for s in ss])
