@@ -1,0 +1,224 @@
+// fwht_batched.hip -- host side of the batched persistent transform: work-list
+// planning, device buffers, and a cached HIP graph per request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <vector>
+
+#include "fwht_internal.hpp"
+#include "wht_batched.hpp"
+
+namespace fwht {
+
+namespace {
+
+constexpr int BTB = 14;   // tile bits of the batched kernel
+constexpr int BNT = 512;  // threads per block
+
+struct Plan {
+    // key
+    float *data = nullptr;
+    int32_t count = 0;
+    int normalize = 0, prec = 0;
+    uint64_t hash = 0;
+    // device state
+    BItem *items = nullptr;
+    int64_t *segs = nullptr;
+    int32_t *counters = nullptr;  // [0] queue, [1] err, [2..] done
+    int32_t ncounters = 0;
+    int32_t nitems = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+std::mutex g_mu;
+std::list<Plan> g_plans;  // most recent first
+constexpr size_t kMaxPlans = 8;
+hipStream_t g_capture = nullptr;
+
+uint64_t fnv(const void *p, size_t n, uint64_t h)
+{
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    return h;
+}
+
+void release(Plan &p)
+{
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.items) (void)hipFree(p.items);
+    if (p.segs) (void)hipFree(p.segs);
+    if (p.counters) (void)hipFree(p.counters);
+    p = Plan{};
+}
+
+int grid_size(int prec, int *out)
+{
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    if (prec == FWHT_PREC_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<BTB, BNT, FWHT_PREC_FP32>, BNT, 0);
+    else
+        e = batched_mfma_occupancy(prec, &per);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    *out = cus * std::max(per, 1);
+    return FWHT_OK;
+}
+
+// Items in hand-out order: STEP1 chunks of the transforms larger than one tile
+// (largest first), then tiles of whole transforms by decreasing size, then
+// the STEP2 items of the large transforms.
+void build_items(const int64_t *off, const int32_t *lg, int32_t count, std::vector<BItem> &items,
+                 std::vector<int64_t> &segs, int32_t &ntid)
+{
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return lg[a] > lg[b]; });
+    ntid = 0;
+    std::vector<std::pair<int32_t, int32_t>> big;  // (transform, tid)
+    for (int32_t i : order)
+        if (lg[i] > BTB) big.push_back({i, ntid++});
+    for (auto &bt : big)
+        for (int32_t c = 0; c < (1 << (lg[bt.first] - BTB)); ++c)
+            items.push_back(BItem{off[bt.first], BK_STEP1, lg[bt.first], c, bt.second, 0, 0});
+    size_t k = 0;
+    while (k < order.size()) {
+        const int32_t m = lg[order[k]];
+        if (m > BTB) { ++k; continue; }
+        const int32_t per = 1 << (BTB - m);
+        BItem it{0, BK_TILE, m, 0, 0, (int32_t)segs.size(), 0};
+        while (k < order.size() && lg[order[k]] == m && it.nseg < per) {
+            segs.push_back(off[order[k]]);
+            ++it.nseg;
+            ++k;
+        }
+        items.push_back(it);
+    }
+    for (auto &bt : big)
+        for (int32_t c = 0; c < (1 << (lg[bt.first] - BTB)); ++c)
+            items.push_back(BItem{off[bt.first], BK_STEP2, lg[bt.first], c, bt.second, 0, 0});
+}
+
+int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec)
+{
+    std::vector<BItem> items;
+    std::vector<int64_t> segs;
+    int32_t ntid = 0;
+    build_items(off, lg, count, items, segs, ntid);
+    if (segs.empty()) segs.push_back(0);
+    p.nitems = (int32_t)items.size();
+    p.ncounters = 2 + std::max(ntid, 1);
+    hipError_t e = hipMalloc(&p.items, sizeof(BItem) * items.size());
+    if (e == hipSuccess) e = hipMalloc(&p.segs, sizeof(int64_t) * segs.size());
+    if (e == hipSuccess) e = hipMalloc(&p.counters, sizeof(int32_t) * (size_t)p.ncounters);
+    if (e != hipSuccess) return fail(FWHT_E_NOMEM, "batched plan: %s", hipGetErrorString(e));
+    e = hipMemcpy(p.items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.segs, segs.data(), sizeof(int64_t) * segs.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batched plan upload");
+
+    int grid = 0;
+    int rc = grid_size(prec, &grid);
+    if (rc) return rc;
+    if (!g_capture) {
+        e = hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+    }
+    BArgs a{};
+    a.data = data;
+    a.items = p.items;
+    a.segs = p.segs;
+    a.nitems = p.nitems;
+    a.normalize = normalize;
+    a.queue = p.counters;
+    a.err = p.counters + 1;
+    a.done = p.counters + 2;
+    // The graph: a small kernel clears the counters (no memset node), then
+    // the persistent kernel drains the work list.
+    e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(256), 0, g_capture, p.counters, p.ncounters);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = launch_batched(prec, a, grid, g_capture);
+    e = hipStreamEndCapture(g_capture, &p.graph);
+    if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    return FWHT_OK;
+}
+
+}  // namespace
+
+hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s)
+{
+    if (prec == FWHT_PREC_FP32)
+        hipLaunchKernelGGL((batched_kernel<BTB, BNT, FWHT_PREC_FP32>), dim3(grid), dim3(BNT), 0, s, a);
+    else
+        return launch_batched_mfma(prec, a, grid, s);
+    return hipGetLastError();
+}
+
+int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec,
+            hipStream_t s)
+{
+    uint64_t h = fnv(off, sizeof(int64_t) * (size_t)count, 0xcbf29ce484222325ull);
+    h = fnv(lg, sizeof(int32_t) * (size_t)count, h);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.begin();
+    for (; it != g_plans.end(); ++it)
+        if (it->data == data && it->count == count && it->normalize == normalize && it->prec == prec &&
+            it->hash == h)
+            break;
+    if (it == g_plans.end()) {
+        if (g_plans.size() >= kMaxPlans) {
+            // An evicted plan's graph may still be in flight on some stream.
+            (void)hipDeviceSynchronize();
+            release(g_plans.back());
+            g_plans.pop_back();
+        }
+        g_plans.push_front(Plan{});
+        Plan &p = g_plans.front();
+        p.data = data;
+        p.count = count;
+        p.normalize = normalize;
+        p.prec = prec;
+        p.hash = h;
+        int rc = make_plan(p, data, off, lg, count, normalize, prec);
+        if (rc) {
+            release(p);
+            g_plans.pop_front();
+            return rc;
+        }
+        it = g_plans.begin();
+    } else if (it != g_plans.begin()) {
+        g_plans.splice(g_plans.begin(), g_plans, it);
+        it = g_plans.begin();
+    }
+    hipError_t e = hipGraphLaunch(it->exec, s);
+    return e == hipSuccess ? FWHT_OK : hip_fail(e, "graph launch");
+}
+
+}  // namespace fwht
+
+extern "C" int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
+                            int normalize, int prec, void *stream)
+{
+    using namespace fwht;
+    if (!data || !offsets || !log2n) return fail(FWHT_E_INVAL, "NULL argument");
+    if (((uintptr_t)data) & 15) return fail(FWHT_E_INVAL, "data must be 16-byte aligned");
+    if (count < 1) return fail(FWHT_E_INVAL, "count must be >= 1");
+    if (prec != FWHT_PREC_FP32 && prec != FWHT_PREC_FP16_MFMA && prec != FWHT_PREC_BF16_MFMA)
+        return fail(FWHT_E_INVAL, "unknown precision %d", prec);
+    for (int32_t t = 0; t < count; ++t) {
+        if (log2n[t] < 2 || log2n[t] > 16) return fail(FWHT_E_RANGE, "log2n[%d] = %d outside [2, 16]", t, log2n[t]);
+        if (offsets[t] < 0 || (offsets[t] & 3)) return fail(FWHT_E_INVAL, "offsets[%d] must be >= 0 and a multiple of 4", t);
+    }
+    return batched(data, offsets, log2n, count, normalize, prec, (hipStream_t)stream);
+}

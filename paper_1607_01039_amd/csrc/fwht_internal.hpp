@@ -11,6 +11,7 @@
 namespace fwht {
 
 struct PassArgs;
+struct BArgs;
 
 // One compiled tile-kernel variant (see wht_tile.hpp): tiles of 2^TB entries,
 // 2^CB contiguous columns, NT threads; COLS = contiguous pass.
@@ -53,6 +54,11 @@ const std::string *tuned_schedule(int dtype, int n);
 int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s);
 int zero_count(uint64_t *count, hipStream_t s);
 float float_threshold(double T);
+
+// batched persistent path (fwht_batched.hip, fwht_mfma.hip)
+hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s);
+hipError_t launch_batched_mfma(int prec, const BArgs &a, int grid, hipStream_t s);
+hipError_t batched_mfma_occupancy(int prec, int *blocks_per_cu);
 
 // streamed Kronecker path (pinned host data), fwht_stream.hip
 int streamed_int(void *host, int dtype, int n, const fwht_thresh_t *th, hipStream_t s);

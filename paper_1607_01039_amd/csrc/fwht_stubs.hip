@@ -3,8 +3,6 @@
 namespace fwht {
 int streamed_int(void *, int, int, const fwht_thresh_t *, hipStream_t) { return fail(FWHT_E_UNSUPPORTED, "streamed path not built"); }
 int mfma_uniform(float *, int, uint64_t, int, int, hipStream_t) { return fail(FWHT_E_UNSUPPORTED, "mfma path not built"); }
-}
-extern "C" {
-int fwht_batched(float *, const int64_t *, const int32_t *, int32_t, int, int, void *) { return fwht::fail(FWHT_E_UNSUPPORTED, "batched not built"); }
-int fwht_norms(const float *, const float *, const double *, const int64_t *, const int32_t *, int32_t, double *, void *) { return fwht::fail(FWHT_E_UNSUPPORTED, "norms not built"); }
+hipError_t launch_batched_mfma(int, const BArgs &, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t batched_mfma_occupancy(int, int *b) { *b = 1; return hipSuccess; }
 }

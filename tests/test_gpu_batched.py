@@ -1,0 +1,114 @@
+"""GPU parity of the batched persistent transform (uneven sizes, one launch
+replayed from a cached HIP graph) against the FP64 oracle.
+
+FP32 tolerance as for fwht_float: normwise (m + 2) * 2^-23 per transform.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1607_01039_amd as F
+    F._lib.lib()
+    return F
+
+
+def per_transform_err(y, ref, off, lg):
+    errs = np.empty(len(off))
+    for t in range(len(off)):
+        sl = slice(int(off[t]), int(off[t]) + (1 << int(lg[t])))
+        r = ref[sl]
+        errs[t] = np.linalg.norm(y[sl].astype(np.float64) - r) / max(np.linalg.norm(r), 1e-300)
+    return errs
+
+
+def run_batched(F, x, off, lg, normalize=True, precision="fp32", reps=1):
+    import torch
+    t = torch.from_numpy(x).cuda()
+    for _ in range(reps):
+        F.fwht_batched_(t, off, lg, normalize=normalize, precision=precision)
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("count,lo,hi,seed", [(1, 16, 16, 1), (3, 2, 4, 2), (57, 2, 16, 3), (300, 8, 16, 4),
+                                              (40, 15, 16, 5), (200, 2, 9, 6)])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_batched_matches_oracle(F, O, count, lo, hi, seed, normalize):
+    lg, off, tot = synth.ragged(count, lo, hi, seed)
+    x = synth.normal(tot, seed + 100)
+    y = run_batched(F, x, off, lg, normalize)
+    ref = O.wht_ragged(x, off, lg, normalize)
+    errs = per_transform_err(y, ref, off, lg)
+    assert np.all(errs <= (lg + 2) * 2.0 ** -23), (errs.max(), lg[np.argmax(errs)])
+
+
+def test_batched_config_4096(F, O):
+    """4096 transforms, sizes 2^U{8..16}, x ~ N(0,1) (seed 4): every transform."""
+    lg, off, tot = synth.ragged(4096, 8, 16, 4)
+    x = synth.normal(tot, 4)
+    y = run_batched(F, x, off, lg, True)
+    ref = O.wht_ragged(x, off, lg, True)
+    errs = per_transform_err(y, ref, off, lg)
+    assert np.all(errs <= (lg + 2) * 2.0 ** -23), errs.max()
+
+
+def test_batched_graph_replays(F, O):
+    """The cached graph is replayed several times with eager work and syncs in
+    between; every replay must give the eager result (Y(Yx) = x after two)."""
+    import torch
+    lg, off, tot = synth.ragged(500, 2, 16, 7)
+    x = synth.normal(tot, 7)
+    ref1 = O.wht_ragged(x, off, lg, True)
+    t = torch.from_numpy(x).cuda()
+    for rep in range(6):
+        F.fwht_batched_(t, off, lg)
+        junk = torch.randn(1 << 20, device="cuda")  # eager work between replays
+        junk.mul_(2.0).sum().item()
+        torch.cuda.synchronize()
+        y = t.cpu().numpy()
+        want = ref1 if rep % 2 == 0 else x.astype(np.float64)
+        errs = per_transform_err(y, want, off, lg)
+        assert np.all(errs <= 2 * (lg + 2) * 2.0 ** -23), (rep, errs.max())
+
+
+def test_batched_permutation_invariant(F, O):
+    """Reordering the list (same transforms at the same places) changes nothing."""
+    lg, off, tot = synth.ragged(300, 2, 16, 8)
+    x = synth.normal(tot, 8)
+    y1 = run_batched(F, x, off, lg)
+    perm = np.random.default_rng(0).permutation(len(off))
+    y2 = run_batched(F, x, off[perm], lg[perm])
+    assert np.array_equal(y1, y2)
+
+
+def test_batched_matches_uniform_path(F, O):
+    """Same-size transforms: the batched kernel and fwht_float agree to rounding."""
+    import torch
+    n, B = 13, 64
+    x = synth.normal((B, 1 << n), 9)
+    off = np.arange(B, dtype=np.int64) << n
+    lg = np.full(B, n, dtype=np.int32)
+    y1 = run_batched(F, x.reshape(-1), off, lg).reshape(B, -1)
+    t = torch.from_numpy(x).cuda()
+    F.fwht_float_(t)
+    y2 = t.cpu().numpy()
+    assert np.max(np.abs(y1 - y2)) <= 1e-5 * np.max(np.abs(y2))
+
+
+def test_batched_rejects_bad_input(F):
+    import torch
+    t = torch.zeros(1 << 10, device="cuda")
+    with pytest.raises(F.FWHTError):
+        F.fwht_batched_(t, np.array([0], np.int64), np.array([17], np.int32))
+    with pytest.raises(F.FWHTError):
+        F.fwht_batched_(t, np.array([2], np.int64), np.array([4], np.int32))
+    with pytest.raises(F.FWHTError):
+        F.fwht_batched_(t, np.array([0], np.int64), np.array([1], np.int32))
