@@ -14,6 +14,12 @@
 
 namespace fwht {
 
+// Zero the queue counter, the completion counters and the error flag.
+__global__ void batched_reset_kernel(int32_t *p, int32_t n)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 namespace {
 
 constexpr int BTB = 14;   // tile bits of the batched kernel

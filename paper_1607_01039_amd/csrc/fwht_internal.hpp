@@ -59,6 +59,8 @@ float float_threshold(double T);
 hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s);
 hipError_t launch_batched_mfma(int prec, const BArgs &a, int grid, hipStream_t s);
 hipError_t batched_mfma_occupancy(int prec, int *blocks_per_cu);
+int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec,
+            hipStream_t s);
 
 // streamed Kronecker path (pinned host data), fwht_stream.hip
 int streamed_int(void *host, int dtype, int n, const fwht_thresh_t *th, hipStream_t s);

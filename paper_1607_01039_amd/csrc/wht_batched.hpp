@@ -42,12 +42,6 @@ struct BArgs {
     int32_t *err;    // [1] set when a wait exceeds its bound
 };
 
-// Zero the queue counter, the completion counters and the error flag.
-__global__ void batched_reset_kernel(int32_t *p, int32_t n)
-{
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
 template <int TB, int NT, int PREC>
 struct BatchedKernel {
     using S = float;

@@ -112,3 +112,60 @@ def test_batched_rejects_bad_input(F):
         F.fwht_batched_(t, np.array([2], np.int64), np.array([4], np.int32))
     with pytest.raises(F.FWHTError):
         F.fwht_batched_(t, np.array([0], np.int64), np.array([1], np.int32))
+
+
+# ---- radix-16 stages on the matrix cores (f16 / bf16 operands, FP32 accumulation)
+# Gate (f16): normwise relative error <= 1e-3 per transform against the FP64
+# oracle.  bf16 keeps 8 significant bits, so its error (~3e-3) is stated, not
+# gated at 1e-3: it is checked against a bound of 1e-2.
+
+@pytest.mark.parametrize("precision,bound", [("fp16", 1e-3), ("bf16", 1e-2)])
+@pytest.mark.parametrize("count,lo,hi,seed", [(1, 16, 16, 1), (3, 2, 4, 2), (57, 2, 16, 3), (300, 8, 16, 4),
+                                              (40, 15, 16, 5)])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_batched_mfma_matches_oracle(F, O, precision, bound, count, lo, hi, seed, normalize):
+    lg, off, tot = synth.ragged(count, lo, hi, seed)
+    x = synth.normal(tot, seed + 100)
+    y = run_batched(F, x, off, lg, normalize, precision=precision)
+    ref = O.wht_ragged(x, off, lg, normalize)
+    errs = per_transform_err(y, ref, off, lg)
+    assert np.all(errs <= bound), (errs.max(), lg[np.argmax(errs)])
+    assert errs.max() > 1e-7  # reduced precision really was used
+
+
+@pytest.mark.parametrize("precision,bound", [("fp16", 1e-3), ("bf16", 1e-2)])
+def test_batched_mfma_config_4096(F, O, precision, bound):
+    lg, off, tot = synth.ragged(4096, 8, 16, 4)
+    x = synth.normal(tot, 4)
+    y = run_batched(F, x, off, lg, True, precision=precision)
+    ref = O.wht_ragged(x, off, lg, True)
+    errs = per_transform_err(y, ref, off, lg)
+    assert np.all(errs <= bound), errs.max()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_float_uniform_mfma(F, O, precision):
+    import torch
+    n, B = 12, 16
+    x = synth.normal((B, 1 << n), 12)
+    t = torch.from_numpy(x).cuda()
+    F.fwht_float_(t, normalize=True, precision=precision)
+    y = t.cpu().numpy()
+    ref = O.wht_batch(x, n, True)
+    err = np.max(np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    assert err <= (1e-3 if precision == "fp16" else 1e-2), err
+    with pytest.raises(F.FWHTError):
+        F.fwht_float_(torch.zeros((1, 1 << 17), device="cuda"), precision=precision)
+
+
+def test_mfma_exact_on_small_integers(F, O):
+    """Inputs that are small integers stay exact in f16 through H_16 stages
+    with power-of-two scales: unnormalised results are bit-exact."""
+    lg = np.array([8, 12, 14, 16], dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(1 << lg.astype(np.int64))[:-1]]).astype(np.int64)
+    tot = int((1 << lg.astype(np.int64)).sum())
+    x = synth.ints(tot, 3, -2, 2, dtype=np.int64).astype(np.float32)
+    y = run_batched(F, x, off, lg, normalize=False, precision="fp16")
+    ref = O.wht_ragged(x, off, lg, False)
+    # f16 represents integers up to 2048 exactly; stage inputs stay below that
+    assert np.array_equal(y.astype(np.float64), ref)
