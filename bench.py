@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n", type=int, default=N_BITS)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (FP32 vs MFMA) and autograd measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -152,6 +154,10 @@ def main():
         "hits": int(np.median(counts)),
     }
 
+    if not args.no_extras:
+        out["batched"] = bench_batched(F, torch, np, synth)
+        out["autograd"] = bench_autograd(F, torch, np, synth)
+
     if not args.no_cpu:
         import oracle
         O = oracle.get()
@@ -173,6 +179,86 @@ def main():
                                     "seconds": round(t_par, 2)}
         del xc
     print(json.dumps(out), flush=True)
+
+
+def _time_replays(torch, fn, reps, flush=None):
+    """Mean device ms of fn() over `reps` calls (each bracketed by events);
+    `flush` (if given) runs before every call, outside the timed interval."""
+    ts = []
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(sorted(ts)[len(ts) // 2])
+
+
+def bench_batched(F, torch, np, synth):
+    """4096 orthonormal transforms of sizes 2^U{8..16}, x ~ N(0,1) (seed 4), one
+    persistent launch per call replayed from the cached graph: FP32 VALU path
+    against the f16 / bf16 radix-16 matrix-core paths.  Warm = data left in
+    the 256 MB Infinity Cache by the previous call; cold = a 1 GiB buffer is
+    streamed between calls.  Accuracy here uses the library's FP64 norm
+    reductions on the GPU: the normwise distance of each reduced-precision
+    result from the FP32 result, and the Parseval defect |sum y^2 - sum x^2| /
+    sum x^2 (the FP64-oracle errors are gated by the test-suite)."""
+    lg, off, tot = synth.ragged(4096, 8, 16, 4)
+    x = torch.from_numpy(synth.normal(tot, 4)).cuda()
+    algo_bytes = 2 * tot * 4
+    flushbuf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    res = {"transforms": 4096, "elements": tot, "algorithmic_bytes": algo_bytes}
+    outs = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        t = x.clone()
+        F.fwht_batched_(t, off, lg, precision=prec)  # builds and caches the graph
+        torch.cuda.synchronize()
+        outs[prec] = t.clone()
+        warm = _time_replays(torch, lambda: F.fwht_batched_(t, off, lg, precision=prec), 30)
+        cold = _time_replays(torch, lambda: F.fwht_batched_(t, off, lg, precision=prec), 10,
+                             flush=lambda: flushbuf.add_(1.0))
+        nr = F.norms(x, outs[prec], off, lg).cpu().numpy()
+        res[prec] = {"ms_warm": round(warm, 4), "ms_cold": round(cold, 4),
+                     "GBs_warm": round(algo_bytes / warm / 1e6, 1), "GBs_cold": round(algo_bytes / cold / 1e6, 1),
+                     "parseval_defect_max": float(f"{np.max(np.abs(nr[:, 1] - nr[:, 0]) / nr[:, 0]):.3e}")}
+        del t
+    ref = outs["fp32"].double()
+    for prec in ("fp16", "bf16"):
+        nr = F.norms(x, outs[prec], off, lg, r=ref).cpu().numpy()
+        res[prec]["diff_vs_fp32_normwise_max"] = float(f"{np.max(np.sqrt(nr[:, 2] / nr[:, 1])):.3e}")
+    res["speedup_fp16_vs_fp32_warm"] = round(res["fp32"]["ms_warm"] / res["fp16"]["ms_warm"], 3)
+    res["speedup_fp16_vs_fp32_cold"] = round(res["fp32"]["ms_cold"] / res["fp16"]["ms_cold"], 3)
+    del flushbuf, outs, ref, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_autograd(F, torch, np, synth):
+    """256 x 2^20 orthonormal transforms: forward + weighted-square loss +
+    backward (the backward runs the same kernel on the gradient)."""
+    n, B = 20, 256
+    x = torch.from_numpy(synth.normal((B, 1 << n), 5)).cuda().requires_grad_(True)
+    w = torch.from_numpy(synth.uniform((B, 1 << n), 55)).cuda()
+    buf = x.detach().clone()
+
+    def step():
+        x.grad = None
+        y = F.fwht(x)
+        (w * y * y).sum().backward()
+
+    step()
+    torch.cuda.synchronize()
+    ms_call = _time_replays(torch, lambda: F.fwht_float_(buf), 10)
+    ms_step = _time_replays(torch, step, 5)
+    res = {"shape": [B, 1 << n], "ms_per_fwht_call": round(ms_call, 4),
+           "GBs_per_call": round(2 * 2 * B * (1 << n) * 4 / ms_call / 1e6, 1),
+           "ms_forward_loss_backward": round(ms_step, 4), "schedule": F.get_schedule("float32", n)}
+    del x, w, buf
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

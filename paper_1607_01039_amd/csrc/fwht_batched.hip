@@ -14,16 +14,21 @@
 
 namespace fwht {
 
-// Zero the queue counter, the completion counters and the error flag.
+// Zero the work-list counter (a kernel node, not a memset node, in the graph).
 __global__ void batched_reset_kernel(int32_t *p, int32_t n)
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+__global__ void __launch_bounds__(BATCH_NT, 1) batched_kernel(BArgs a)
+{
+    BatchedKernel<BATCH_TB, BATCH_NT>::run(a);
+}
+
 namespace {
 
-constexpr int BTB = 14;   // tile bits of the batched kernel
-constexpr int BNT = 512;  // threads per block
+constexpr int BTB = BATCH_TB;  // tile bits of the batched kernel
+constexpr int BNT = BATCH_NT;  // threads per block
 
 struct Plan {
     // key
@@ -34,7 +39,7 @@ struct Plan {
     // device state
     BItem *items = nullptr;
     int64_t *segs = nullptr;
-    int32_t *counters = nullptr;  // [0] queue, [1] err, [2..] done
+    int32_t *counters = nullptr;  // [0] work-list counter
     int32_t ncounters = 0;
     int32_t nitems = 0;
     hipGraphExec_t exec = nullptr;
@@ -70,7 +75,7 @@ int grid_size(int prec, int *out)
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
     if (prec == FWHT_PREC_FP32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel<BTB, BNT, FWHT_PREC_FP32>, BNT, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel, BNT, 0);
     else
         e = batched_mfma_occupancy(prec, &per);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
@@ -78,28 +83,20 @@ int grid_size(int prec, int *out)
     return FWHT_OK;
 }
 
-// Items in hand-out order: STEP1 chunks of the transforms larger than one tile
-// (largest first), then tiles of whole transforms by decreasing size, then
-// the STEP2 items of the large transforms.
+// Tiles in hand-out order: transforms sorted by decreasing size; each tile
+// gathers 2^(16-m) transforms of one size 2^m (the last of a size may hold
+// fewer).
 void build_items(const int64_t *off, const int32_t *lg, int32_t count, std::vector<BItem> &items,
-                 std::vector<int64_t> &segs, int32_t &ntid)
+                 std::vector<int64_t> &segs)
 {
     std::vector<int32_t> order((size_t)count);
     for (int32_t i = 0; i < count; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return lg[a] > lg[b]; });
-    ntid = 0;
-    std::vector<std::pair<int32_t, int32_t>> big;  // (transform, tid)
-    for (int32_t i : order)
-        if (lg[i] > BTB) big.push_back({i, ntid++});
-    for (auto &bt : big)
-        for (int32_t c = 0; c < (1 << (lg[bt.first] - BTB)); ++c)
-            items.push_back(BItem{off[bt.first], BK_STEP1, lg[bt.first], c, bt.second, 0, 0});
     size_t k = 0;
     while (k < order.size()) {
         const int32_t m = lg[order[k]];
-        if (m > BTB) { ++k; continue; }
         const int32_t per = 1 << (BTB - m);
-        BItem it{0, BK_TILE, m, 0, 0, (int32_t)segs.size(), 0};
+        BItem it{m, (int32_t)segs.size(), 0, 0};
         while (k < order.size() && lg[order[k]] == m && it.nseg < per) {
             segs.push_back(off[order[k]]);
             ++it.nseg;
@@ -107,20 +104,15 @@ void build_items(const int64_t *off, const int32_t *lg, int32_t count, std::vect
         }
         items.push_back(it);
     }
-    for (auto &bt : big)
-        for (int32_t c = 0; c < (1 << (lg[bt.first] - BTB)); ++c)
-            items.push_back(BItem{off[bt.first], BK_STEP2, lg[bt.first], c, bt.second, 0, 0});
 }
 
 int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec)
 {
     std::vector<BItem> items;
     std::vector<int64_t> segs;
-    int32_t ntid = 0;
-    build_items(off, lg, count, items, segs, ntid);
-    if (segs.empty()) segs.push_back(0);
+    build_items(off, lg, count, items, segs);
     p.nitems = (int32_t)items.size();
-    p.ncounters = 2 + std::max(ntid, 1);
+    p.ncounters = 1;
     hipError_t e = hipMalloc(&p.items, sizeof(BItem) * items.size());
     if (e == hipSuccess) e = hipMalloc(&p.segs, sizeof(int64_t) * segs.size());
     if (e == hipSuccess) e = hipMalloc(&p.counters, sizeof(int32_t) * (size_t)p.ncounters);
@@ -143,8 +135,6 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
     a.nitems = p.nitems;
     a.normalize = normalize;
     a.queue = p.counters;
-    a.err = p.counters + 1;
-    a.done = p.counters + 2;
     // The graph: a small kernel clears the counters (no memset node), then
     // the persistent kernel drains the work list.
     e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
@@ -165,7 +155,7 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
 hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s)
 {
     if (prec == FWHT_PREC_FP32)
-        hipLaunchKernelGGL((batched_kernel<BTB, BNT, FWHT_PREC_FP32>), dim3(grid), dim3(BNT), 0, s, a);
+        hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BNT), 0, s, a);
     else
         return launch_batched_mfma(prec, a, grid, s);
     return hipGetLastError();

@@ -13,9 +13,9 @@ namespace fwht {
 hipError_t launch_batched_mfma(int prec, const BArgs &a, int grid, hipStream_t s)
 {
     if (prec == FWHT_PREC_FP16_MFMA)
-        hipLaunchKernelGGL(batched_mfma_kernel<FWHT_PREC_FP16_MFMA>, dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(batched_mfma_kernel<FWHT_PREC_FP16_MFMA>, dim3(grid), dim3(1024), 0, s, a);
     else if (prec == FWHT_PREC_BF16_MFMA)
-        hipLaunchKernelGGL(batched_mfma_kernel<FWHT_PREC_BF16_MFMA>, dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(batched_mfma_kernel<FWHT_PREC_BF16_MFMA>, dim3(grid), dim3(1024), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -25,9 +25,9 @@ hipError_t batched_mfma_occupancy(int prec, int *blocks_per_cu)
 {
     if (prec == FWHT_PREC_FP16_MFMA)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batched_mfma_kernel<FWHT_PREC_FP16_MFMA>,
-                                                            512, 0);
+                                                            1024, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batched_mfma_kernel<FWHT_PREC_BF16_MFMA>,
-                                                        512, 0);
+                                                        1024, 0);
 }
 
 // `batch` transforms of 2^n consecutive entries through the batched kernel.

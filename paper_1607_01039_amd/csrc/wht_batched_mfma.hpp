@@ -13,12 +13,20 @@
 // an exact power of two) is exact in both formats.  Stage bits that a work
 // item does not transform get an identity factor instead of H_2.
 //
-// Tile of 2^14 entries, 512 threads, 32 entries per thread, two layouts:
-//   MA (load/store): registers {0,1,11,12,13}, lanes {2..7}, waves {8,9,10};
-//        MFMA on {0,1,6,7} (registers 0,1 + lanes 4,5), VALU on {11,12,13}.
-//   MB: registers {2,3,8,9,10}, lanes {0,1,6,7,4,5}, waves {11,12,13};
-//        MFMA on {2,3,4,5} (registers 2,3 + lanes 4,5), VALU on {8,9,10}.
-// The remaining bits are FP32 VALU butterflies, as in the FP32 kernel.
+// Tile of 2^16 entries (as the FP32 kernel), 1024 threads, 64 entries per
+// thread, two layouts (register bits listed in register-index order):
+//   MA (load): registers {0,1,12,13,14,15}, lanes {2..7}, waves {8..11};
+//        MFMA on {0,1,6,7} (registers 0,1 + lanes 4,5), VALU on {12..15}.
+//   MB: registers {2,3,8,9,10,11}, lanes {0,1,6,7,4,5}, waves {12..15};
+//        MFMA on {2,3,4,5}, VALU on {8..11}.
+//   MC (store): registers {0,1,12,13,14,11}, lanes {2..7}, waves {8,9,10,15}:
+//        16-byte stores of four consecutive entries.
+// MA -> MB goes through LDS as f16/bf16: the values are the operands of MB's
+// MFMA stage, which rounds them to that format anyway, so storing them
+// rounded changes nothing and halves the LDS footprint (the whole 2^16 tile
+// in 128 KiB).  MB -> MC goes through the same LDS as FP32 values in two
+// halves: bit 11 is the last register bit of both, so each half of every
+// thread's registers maps to one half of the tile.
 #pragma once
 #include "wht_batched.hpp"
 
@@ -29,19 +37,26 @@ typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 struct XLayout {
-    int reg[5];
+    int reg[6];
     int lane[6];
-    int wave[3];
+    int wave[4];
 };
 
-constexpr XLayout XL_A{{0, 1, 11, 12, 13}, {2, 3, 4, 5, 6, 7}, {8, 9, 10}};
-constexpr XLayout XL_B{{2, 3, 8, 9, 10}, {0, 1, 6, 7, 4, 5}, {11, 12, 13}};
+constexpr XLayout XL_A{{0, 1, 12, 13, 14, 15}, {2, 3, 4, 5, 6, 7}, {8, 9, 10, 11}};
+constexpr XLayout XL_B{{2, 3, 8, 9, 10, 11}, {0, 1, 6, 7, 4, 5}, {12, 13, 14, 15}};
+constexpr XLayout XL_C{{0, 1, 12, 13, 14, 11}, {2, 3, 4, 5, 6, 7}, {8, 9, 10, 15}};
 
 constexpr uint32_t xl_reg_part(const XLayout &L, uint32_t j)
 {
     uint32_t r = 0;
-    for (int q = 0; q < 5; ++q)
+    for (int q = 0; q < 6; ++q)
         if ((j >> q) & 1u) r |= 1u << L.reg[q];
+    return r;
+}
+constexpr uint32_t xl_lane_mask(const XLayout &L)
+{
+    uint32_t r = 0;
+    for (int q = 0; q < 6; ++q) r |= 1u << L.lane[q];
     return r;
 }
 
@@ -92,55 +107,86 @@ struct MfmaOp<FWHT_PREC_BF16_MFMA> {
 
 template <int PREC>
 struct BatchedMfmaKernel {
-    static constexpr int TB = 14, NT = 512, E = 32, VEC = 4;
-    static constexpr uint32_t FULL = lowmask(TB);
-    static constexpr int LDS_ELEMS = (1 << TB) + (1 << TB) / 32;
-    using Base = BatchedKernel<14, 512, FWHT_PREC_FP32>;  // address helpers
+    static constexpr int TB = 16, NT = 1024, E = 64, VEC = 4;
+    static constexpr int LDS_HALFS = (1 << TB) + (1 << TB) / 32;
+    using Base = BatchedKernel<16, 1024>;  // address, fetch and item helpers
 
-    // Thread part of the tile index in layout WHICH.
     template <int WHICH>
-    __device__ static __forceinline__ uint32_t tpart(uint32_t t)
+    __device__ static __forceinline__ uint32_t lane_part(uint32_t lane)
     {
-        constexpr XLayout L = WHICH == 0 ? XL_A : XL_B;
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
         uint32_t r = 0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) r |= ((t >> q) & 1u) << L.lane[q];
+        for (int q = 0; q < 6; ++q) r |= ((lane >> q) & 1u) << L.lane[q];
+        return r;
+    }
+    template <int WHICH>
+    __device__ static __forceinline__ uint32_t wave_part(uint32_t wave)
+    {
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
+        uint32_t r = 0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) r |= ((t >> (6 + q)) & 1u) << L.wave[q];
+        for (int q = 0; q < 4; ++q) r |= ((wave >> q) & 1u) << L.wave[q];
         return r;
     }
 
-    template <int WHICH>
-    __device__ static __forceinline__ void to_lds(float *lds, const float (&v)[E], uint32_t t)
+    // MA -> MB through LDS in the operand format (see the file comment).
+    __device__ static __forceinline__ void transpose_ab(uint16_t *lds, float (&v)[E], uint32_t lane, uint32_t wave)
     {
-        constexpr XLayout L = WHICH == 0 ? XL_A : XL_B;
-        const uint32_t tb = lds_pad(tpart<WHICH>(t));
+        const uint32_t ta = lds_pad(lane_part<0>(lane) | wave_part<0>(wave));
+        const uint32_t tb = lds_pad(lane_part<1>(lane) | wave_part<1>(wave));
+        __syncthreads();
         static_for<0, E>([&](auto J) {
-            constexpr uint32_t jp = xl_reg_part(L, decltype(J)::value);
-            lds[tb + jp + (jp >> 5)] = v[decltype(J)::value];
+            constexpr uint32_t jp = xl_reg_part(XL_A, decltype(J)::value);
+            lds[ta + jp + (jp >> 5)] = to_half_bits<PREC>(v[decltype(J)::value]);
+        });
+        __syncthreads();
+        static_for<0, E>([&](auto J) {
+            constexpr uint32_t jp = xl_reg_part(XL_B, decltype(J)::value);
+            v[decltype(J)::value] = from_half_bits(lds[tb + jp + (jp >> 5)]);
         });
     }
 
-    template <int WHICH>
-    __device__ static __forceinline__ void from_lds(const float *lds, float (&v)[E], uint32_t t)
+    // MB -> MC through LDS as FP32, one half (tile bit 11 = register index 5)
+    // at a time; the half-tile index drops bit 11.
+    __device__ static __forceinline__ uint32_t drop11(uint32_t i) { return (i & 0x7ffu) | ((i >> 1) & ~0x7ffu); }
+
+    __device__ static __forceinline__ void transpose_bc(float *lds, float (&v)[E], uint32_t lane, uint32_t wave)
     {
-        constexpr XLayout L = WHICH == 0 ? XL_A : XL_B;
-        const uint32_t tb = lds_pad(tpart<WHICH>(t));
-        static_for<0, E>([&](auto J) {
-            constexpr uint32_t jp = xl_reg_part(L, decltype(J)::value);
-            v[decltype(J)::value] = lds[tb + jp + (jp >> 5)];
+        const uint32_t tb = lds_pad(drop11(lane_part<1>(lane) | wave_part<1>(wave)));
+        const uint32_t tc = lds_pad(drop11(lane_part<2>(lane) | wave_part<2>(wave)));
+        static_for<0, 2>([&](auto H0) {
+            constexpr int H = decltype(H0)::value;
+            __syncthreads();
+            static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
+                constexpr uint32_t jp = xl_reg_part(XL_B, decltype(J)::value);
+                constexpr uint32_t jq = (jp & 0x7ffu) | ((jp >> 1) & ~0x7ffu);
+                lds[tb + jq + (jq >> 5)] = v[decltype(J)::value];
+            });
+            __syncthreads();
+            static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
+                constexpr uint32_t jp = xl_reg_part(XL_C, decltype(J)::value);
+                constexpr uint32_t jq = (jp & 0x7ffu) | ((jp >> 1) & ~0x7ffu);
+                v[decltype(J)::value] = lds[tc + jq + (jq >> 5)];
+            });
         });
     }
 
-    // FP32 butterflies on register bits q = 2, 3, 4 of the layout that `act`
-    // selects (tile bits L.reg[2..4]).
-    template <int WHICH>
-    __device__ static __forceinline__ void valu_stages(float (&v)[E], uint32_t act)
+    __device__ static __forceinline__ float from_half_bits(uint16_t h)
     {
-        constexpr XLayout L = WHICH == 0 ? XL_A : XL_B;
-        static_for<2, 5>([&](auto Q) {
+        if constexpr (PREC == FWHT_PREC_FP16_MFMA) return (float)__builtin_bit_cast(_Float16, h);
+        else return __builtin_bit_cast(float, (uint32_t)h << 16);
+    }
+
+    // FP32 butterflies on register indices Q0..Q1-1 of the layout whose tile
+    // bits are below MM.
+    template <int WHICH, int Q0, int Q1, int MM>
+    __device__ static __forceinline__ void valu_stages(float (&v)[E])
+    {
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
+        static_for<Q0, Q1>([&](auto Q) {
             constexpr int q = decltype(Q)::value;
-            if ((act >> L.reg[q]) & 1u) {
+            if constexpr (L.reg[q] < MM) {
 #pragma unroll
                 for (int j = 0; j < E; ++j)
                     if (!((j >> q) & 1)) bfly(v[j], v[j | (1 << q)]);
@@ -148,162 +194,155 @@ struct BatchedMfmaKernel {
         });
     }
 
-    // One MFMA stage over K = {reg 0, reg 1, lane 4, lane 5} of the layout:
-    // A[m][k] = prod over the four bits b of (act_b ? H_2[m_b][k_b] : [m_b == k_b]),
-    // times 2^-ceil(a/2) for a active bits (exact).  Returns the number of
-    // active bits (0: nothing done).
-    template <int WHICH>
-    __device__ static __forceinline__ int mfma_stage(float (&v)[E], uint32_t act, uint32_t lane)
+    // One MFMA stage over K = {register 0, register 1, lane 4, lane 5}:
+    // A[m][k] = prod over the four bits b of (b < MM ? H_2[m_b][k_b] : [m_b == k_b]),
+    // scaled by 2^-ceil(a/2) for a active bits (exact).  Returns ceil(a/2).
+    template <int WHICH, int MM>
+    __device__ static __forceinline__ int mfma_stage(float (&v)[E], uint32_t lane)
     {
-        constexpr XLayout L = WHICH == 0 ? XL_A : XL_B;
-        const uint32_t kb = ((act >> L.reg[0]) & 1u) | (((act >> L.reg[1]) & 1u) << 1) |
-                            (((act >> L.lane[4]) & 1u) << 2) | (((act >> L.lane[5]) & 1u) << 3);
-        const int na = __builtin_popcount(kb);
-        if (na == 0) return 0;
-        // A operand: lane holds A[m = lane mod 16][k = 4 (lane div 16) + i].
-        const uint32_t mrow = lane & 15u;
-        const float sc = 1.0f / (float)(1u << ((na + 1) / 2));
-        uint16_t a[4];
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
+        constexpr uint32_t kb = (L.reg[0] < MM ? 1u : 0u) | (L.reg[1] < MM ? 2u : 0u) |
+                                (L.lane[4] < MM ? 4u : 0u) | (L.lane[5] < MM ? 8u : 0u);
+        constexpr int na = cpopc(kb);
+        if constexpr (na == 0) {
+            return 0;
+        } else {
+            constexpr int sh = (na + 1) / 2;
+            // A operand: lane holds A[m = lane mod 16][k = 4 (lane div 16) + i].
+            const uint32_t mrow = lane & 15u;
+            const float sc = 1.0f / (float)(1u << sh);
+            uint16_t a[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t k = 4u * (lane >> 4) + (uint32_t)i;
-            float val = sc;
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t mb = (mrow >> b) & 1u, kk = (k >> b) & 1u;
-                if ((kb >> b) & 1u) {
-                    if (mb & kk) val = -val;
-                } else if (mb != kk) {
-                    val = 0.f;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t k = 4u * (lane >> 4) + (uint32_t)i;
+                float val = sc;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t mb = (mrow >> b) & 1u, kk = (k >> b) & 1u;
+                    if ((kb >> b) & 1u) {
+                        if (mb & kk) val = -val;
+                    } else if (mb != kk) {
+                        val = 0.f;
+                    }
                 }
+                a[i] = to_half_bits<PREC>(val);
             }
-            a[i] = to_half_bits<PREC>(val);
+            // E/4 independent 16x16 blocks: register indices 2 and up.  The
+            // scheduling fences keep one block's operands live at a time.
+#pragma unroll
+            for (int blk = 0; blk < E / 4; ++blk) {
+                uint16_t b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) b[i] = to_half_bits<PREC>(v[(blk << 2) | i]);
+                const float4_t d = MfmaOp<PREC>::run(a, b);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[(blk << 2) | i] = d[i];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            return sh;
         }
-        // Eight independent 16x16 blocks: register bits 2, 3, 4.
-#pragma unroll
-        for (int blk = 0; blk < 8; ++blk) {
-            uint16_t b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) b[i] = to_half_bits<PREC>(v[(blk << 2) | i]);
-            const float4_t d = MfmaOp<PREC>::run(a, b);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[(blk << 2) | i] = d[i];
-        }
-        return na;
     }
 
-    template <int KIND>
-    __device__ static __forceinline__ void load(const BArgs &a, const BItem &I, float (&v)[E], uint32_t t)
+    template <int MM>
+    __device__ static __forceinline__ void load(const BArgs &a, const BItem &I, float (&v)[E], uint32_t lane,
+                                                uint32_t wave)
     {
-        const uint32_t tp = tpart<0>(t);
+        constexpr uint32_t LM = xl_lane_mask(XL_A);
+        const uint32_t lp = lane_part<0>(lane), wp = wave_part<0>(wave);
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = xl_reg_part(XL_A, (uint32_t)(jt << 2));
-            const int64_t off = Base::template addr<KIND>(I, a.segs, jp | tp);
+            const float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
             v4u q = {0u, 0u, 0u, 0u};
-            if (off >= 0) q = *reinterpret_cast<const v4u *>(a.data + off);
+            if (p) q = *reinterpret_cast<const v4u *>(p);
             const float *qs = reinterpret_cast<const float *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
         });
     }
 
-    template <int KIND>
-    __device__ static __forceinline__ void store(const BArgs &a, const BItem &I, const float (&v)[E], uint32_t t)
+    // 16-byte stores from a layout whose register indices 0, 1 are tile bits
+    // 0, 1 (MA or MC).
+    template <int WHICH, int MM>
+    __device__ static __forceinline__ void store_vec(const BArgs &a, const BItem &I, const float (&v)[E],
+                                                     uint32_t lane, uint32_t wave)
     {
-        const uint32_t tp = tpart<0>(t);
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
+        static_assert(L.reg[0] == 0 && L.reg[1] == 1, "vector layout");
+        constexpr uint32_t LM = xl_lane_mask(L);
+        const uint32_t lp = lane_part<WHICH>(lane), wp = wave_part<WHICH>(wave);
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
-            constexpr uint32_t jp = xl_reg_part(XL_A, (uint32_t)(jt << 2));
-            const int64_t off = Base::template addr<KIND>(I, a.segs, jp | tp);
+            constexpr uint32_t jp = xl_reg_part(L, (uint32_t)(jt << 2));
+            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
             v4u q;
             float *qs = reinterpret_cast<float *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
-            if (off >= 0) *reinterpret_cast<v4u *>(a.data + off) = q;
+            if (p) *reinterpret_cast<v4u *>(p) = q;
         });
     }
 
-    template <int KIND>
-    __device__ static __forceinline__ void item(const BArgs &a, const BItem &I, float *lds, uint32_t t)
+    template <int WHICH, int MM>
+    __device__ static __forceinline__ void store(const BArgs &a, const BItem &I, const float (&v)[E], uint32_t lane,
+                                                 uint32_t wave)
     {
-        uint32_t act;
-        if constexpr (KIND == BK_TILE) act = lowmask(I.m);
-        else if constexpr (KIND == BK_STEP1) act = FULL;
-        else act = lowmask(I.m - TB) << (2 * TB - I.m);
+        constexpr XLayout L = WHICH == 0 ? XL_A : WHICH == 1 ? XL_B : XL_C;
+        constexpr uint32_t LM = xl_lane_mask(L);
+        const uint32_t lp = lane_part<WHICH>(lane), wp = wave_part<WHICH>(wave);
+        static_for<0, E>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            constexpr uint32_t jp = xl_reg_part(L, (uint32_t)j);
+            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
+            if (p) *p = v[j];
+        });
+    }
+
+    template <int MM>
+    __device__ static __forceinline__ void item(const BArgs &a, const BItem &I, uint16_t *lds, uint32_t t)
+    {
         const uint32_t lane = t & 63u;
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
         float v[E];
-        load<KIND>(a, I, v, t);
-        // scale bookkeeping: the MFMA stages multiply by 2^-ceil(a/2) each
-        int shift = mfma_stage<0>(v, act, lane);
-        shift = (shift + 1) / 2;
-        valu_stages<0>(v, act);
-        constexpr uint32_t BBITS = (1u << 2) | (1u << 3) | (1u << 4) | (1u << 5) | (1u << 8) | (1u << 9) | (1u << 10);
-        if (act & BBITS) {
-            __syncthreads();
-            to_lds<0>(lds, v, t);
-            __syncthreads();
-            from_lds<1>(lds, v, t);
-            const int nb = mfma_stage<1>(v, act, lane);
-            shift += (nb + 1) / 2;
-            valu_stages<1>(v, act);
-            __syncthreads();
-            to_lds<1>(lds, v, t);
-            __syncthreads();
-            from_lds<0>(lds, v, t);
+        load<MM>(a, I, v, lane, wave);
+        int shift = mfma_stage<0, MM>(v, lane);
+        valu_stages<0, 2, 6, MM>(v);
+        constexpr bool needB = MM > 2;  // MB owns bits 2..5 and 8..11
+        if constexpr (needB) {
+            transpose_ab(lds, v, lane, wave);
+            shift += mfma_stage<1, MM>(v, lane);
+            valu_stages<1, 2, 6, MM>(v);
         }
-        // Undo the stage scales; apply 2^(-m/2) on the last step.
+        // Undo the stage scales; 2^(-m/2) when normalising.
         float sc = (float)(1u << shift);
-        if (a.normalize && KIND != BK_STEP1) sc *= (float)(1.0 / sqrt((double)(1ull << I.m)));
+        if (a.normalize) sc *= (float)(1.0 / sqrt((double)(1ull << MM)));
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] *= sc;
-        store<KIND>(a, I, v, t);
+        if constexpr (needB) {
+            transpose_bc(reinterpret_cast<float *>(lds), v, lane, wave);
+            store_vec<2, MM>(a, I, v, lane, wave);
+        } else {
+            store_vec<0, MM>(a, I, v, lane, wave);
+        }
     }
 
     __device__ static __forceinline__ void run(const BArgs &a)
     {
-        __shared__ float lds[LDS_ELEMS];
+        __shared__ uint16_t lds[LDS_HALFS];
         __shared__ int32_t s_item;
         const uint32_t t = threadIdx.x;
         for (int32_t it = Base::fetch(a, &s_item, t); it < a.nitems; it = Base::fetch(a, &s_item, t)) {
-            BItem I = a.items[it];
-            I.kind = __builtin_amdgcn_readfirstlane(I.kind);
-            I.m = __builtin_amdgcn_readfirstlane(I.m);
-            I.sub = __builtin_amdgcn_readfirstlane(I.sub);
-            I.tid = __builtin_amdgcn_readfirstlane(I.tid);
-            I.seg0 = __builtin_amdgcn_readfirstlane(I.seg0);
-            I.nseg = __builtin_amdgcn_readfirstlane(I.nseg);
-            if (I.kind == BK_STEP2) {
-                if (__builtin_amdgcn_readfirstlane(t >> 6) == 0) {
-                    const int32_t need = 1 << (I.m - TB);
-                    for (uint32_t spins = 0;; ++spins) {
-                        const int32_t c = __builtin_amdgcn_readfirstlane(
-                            __hip_atomic_load(&a.done[I.tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                        if (c >= need) break;
-                        if (spins > (1u << 26)) {
-                            if (t == 0) atomicExch(a.err, 1);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                }
-                __syncthreads();
-                __threadfence();
-            }
-            if (I.kind == BK_TILE) item<BK_TILE>(a, I, lds, t);
-            else if (I.kind == BK_STEP1) item<BK_STEP1>(a, I, lds, t);
-            else item<BK_STEP2>(a, I, lds, t);
-            __syncthreads();  // LDS reuse by the next item
-            if (I.kind == BK_STEP1) {
-                __threadfence();
-                __syncthreads();
-                if (t == 0) atomicAdd(&a.done[I.tid], 1);
-            }
+            const BItem I = Base::read_item(a, it);
+            static_for<2, TB + 1>([&](auto M0) {
+                constexpr int MM = decltype(M0)::value;
+                if (I.m == MM) item<MM>(a, I, lds, t);
+            });
         }
     }
 };
 
 template <int PREC>
-__global__ void __launch_bounds__(512, 2) batched_mfma_kernel(BArgs a)
+__global__ void __launch_bounds__(1024, 1) batched_mfma_kernel(BArgs a)
 {
     BatchedMfmaKernel<PREC>::run(a);
 }
