@@ -78,10 +78,12 @@ typedef struct {
  *   data  : 2^n int32 (dtype FWHT_I32, n <= 30) or int64 (FWHT_I64) entries,
  *           16-byte aligned.  A device pointer selects the in-HBM path
  *           (n <= 34, asynchronous).  A pinned host pointer selects the
- *           streamed Kronecker path (FWHT_I64 only, 10 <= n <= 40): the array
- *           is split as H_{2^(n-L)} (x) H_{2^L} and both factors are applied
- *           chunk by chunk through device staging buffers; the call is
- *           synchronous with respect to the host.
+ *           streamed Kronecker path (10 <= n <= 40): the array is split as
+ *           H_{2^(n-L)} (x) H_{2^L}, L = ceil(n/2), and both factors are
+ *           applied chunk by chunk (default 2^30-byte chunks, environment
+ *           FWHT_STREAM_CHUNK_BYTES) through three device staging buffers
+ *           the library allocates and keeps; the call is synchronous with
+ *           respect to the host (it first waits for `stream`).
  *   th    : optional (NULL = none).  Fused into the last pass; *count is
  *           zeroed by the call itself.  On the synchronous path the call
  *           returns FWHT_E_CAPACITY when the true count exceeds cap.

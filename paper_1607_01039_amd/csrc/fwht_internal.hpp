@@ -39,6 +39,8 @@ struct Epilogue {
     void *val = nullptr;
     uint64_t cap = 0;
     uint64_t *count = nullptr;
+    uint32_t kshift = 0, kL = 0;  // hit-index remap (see PassArgs)
+    uint64_t kbase = 0;
 };
 
 int fail(int code, const char *fmt, ...);
@@ -52,6 +54,7 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
 std::string schedule_for(int dtype, int n);
 const std::string *tuned_schedule(int dtype, int n);
 int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s);
+int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, const Epilogue &epi, hipStream_t s);
 int zero_count(uint64_t *count, hipStream_t s);
 float float_threshold(double T);
 

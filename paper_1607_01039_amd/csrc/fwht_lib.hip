@@ -194,6 +194,9 @@ int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi,
         }
         const bool last = p + 1 == passes.size();
         if (last) {
+            a.kshift = epi.kshift;
+            a.kL = epi.kL;
+            a.kbase = epi.kbase;
             a.do_scale = epi.do_scale;
             a.scale = epi.scale;
             a.thresh = epi.thresh;
@@ -212,6 +215,52 @@ int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi,
             g_trace_names.push_back(std::string(v.name) + ":" + std::to_string(ps.lo) + "+" + std::to_string(ps.r));
             g_trace_used = (int)p + 2;
         }
+    }
+    return FWHT_OK;
+}
+
+// Transform bits [lo, lo + nbits) of `total` entries (a multiple of
+// 2^(lo + nbits)) with strided passes only: balanced passes of at most 9 bits,
+// each on the variant whose tile height equals its bit count, over 256-byte
+// row segments (512-byte when a pass takes a single bit).  The epilogue goes
+// on the last pass.
+int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, const Epilogue &epi, hipStream_t s)
+{
+    if (nbits <= 0) return FWHT_OK;
+    const int cb = dtype == FWHT_I64 ? 5 : 6;
+    const int np = (nbits + 8) / 9;
+    int done = lo;
+    for (int i = 0; i < np; ++i) {
+        const int r = nbits / np + (i < nbits % np ? 1 : 0);
+        const int c = r == 1 ? cb + 1 : cb;
+        const std::string name = "S" + std::to_string(c + r) + "c" + std::to_string(c);
+        const Variant *v = find_variant(dtype, name);
+        if (!v) return fail(FWHT_E_UNSUPPORTED, "no variant %s", name.c_str());
+        if (done < v->CB) return fail(FWHT_E_INVAL, "strided range starts below the row segment");
+        PassArgs a{};
+        a.total = total;
+        a.b = done;
+        a.colblocks = 1ull << (done - v->CB);
+        a.act = lowmask(r) << v->CB;
+        const uint64_t rows = total >> done;
+        a.ntiles = ((rows + (1ull << (v->TB - v->CB)) - 1) >> (v->TB - v->CB)) * a.colblocks;
+        if (i + 1 == np) {
+            a.kshift = epi.kshift;
+            a.kL = epi.kL;
+            a.kbase = epi.kbase;
+            a.do_scale = epi.do_scale;
+            a.scale = epi.scale;
+            a.thresh = epi.thresh;
+            a.T = epi.T;
+            a.Tf = epi.Tf;
+            a.hit_idx = (unsigned long long *)epi.idx;
+            a.hit_val = epi.val;
+            a.cap = epi.cap;
+            a.count = (unsigned long long *)epi.count;
+        }
+        hipError_t e = v->launch(buf, a, s);
+        if (e != hipSuccess) return hip_fail(e, "strided pass launch");
+        done += r;
     }
     return FWHT_OK;
 }
@@ -312,6 +361,7 @@ int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream
     const bool dev = is_device_pointer(data, &pinned);
     if (!dev) {
         if (!pinned) return fail(FWHT_E_INVAL, "data is neither device nor pinned host memory");
+        if (th && th->cap > 0 && (!th->idx || !th->val)) return fail(FWHT_E_INVAL, "threshold: idx/val NULL");
         return streamed_int(data, dtype, n, th, s);
     }
     if (n > 34) return fail(FWHT_E_RANGE, "in-HBM transforms are limited to n <= 34");

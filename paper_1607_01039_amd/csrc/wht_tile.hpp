@@ -138,6 +138,11 @@ struct PassArgs {
     void *hit_val;
     uint64_t cap;
     unsigned long long *count;
+    // index of a hit: k = ((off >> kshift) << kL | off mod 2^kshift) + kbase,
+    // the identity (k = off) when all three are 0; the streamed column phase
+    // uses it to report positions in the whole array
+    uint32_t kshift, kL;
+    uint64_t kbase;
 };
 
 template <class S> struct Arith;
@@ -177,6 +182,7 @@ __device__ __forceinline__ void emit_hits(bool hit, uint64_t k, S v, const PassA
     if (hit) {
         unsigned long long slot = base + below;
         if (slot < a.cap) {
+            k = (((k >> a.kshift) << a.kL) | (k & ((1ull << a.kshift) - 1ull))) + a.kbase;
             a.hit_idx[slot] = k;
             ((S *)a.hit_val)[slot] = v;
         }
