@@ -14,13 +14,16 @@ Prints ONE JSON line (see the keys below), including
   roofline     : the dominant pass kernel's algorithmic bytes per launch
                  (read 2^n * 4 B + write 2^n * 4 B) over its mean device time
                  measured with HIP events on its launch stream, against the
-                 8 TB/s HBM peak;
+                 8 TB/s HBM peak; `traffic` = that pass's HBM bytes per launch
+                 from the rocprofv3 counter summary in profiles/ (null when
+                 the kernel sources changed since it was taken);
   cpu_baseline : the oracle (Fig. 1 butterflies, one thread) timed on this
                  host on the same n = 30 input.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +37,35 @@ N_BITS = 30
 SEED = 2
 P_NOISE = 0.45
 THRESH = 6 * (1 << 15)
+# HBM bytes per pass measured with rocprofv3 counters (FETCH_SIZE, WRITE_SIZE),
+# valid only for the kernel sources they were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_int32_n30.txt")
+KERNEL_SOURCES = ("paper_1607_01039_amd/csrc/wht_tile.hpp", "paper_1607_01039_amd/csrc/fwht_variants_int32.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(pass_name):
+    """HBM bytes per launch of `pass_name` from the committed counter summary,
+    or None when there is none or the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    except OSError:
+        return None
+    rec = {ln[0]: ln[1:] for ln in lines}
+    if rec.get("source_hash", [None])[0] != kernel_source_hash():
+        return None
+    for ln in lines:
+        if ln[0] == "pass" and ln[1] == pass_name:
+            return int(ln[ln.index("traffic_bytes") + 1])
+    return None
 
 
 def log(msg):
@@ -49,6 +81,9 @@ def main():
     ap.add_argument("--n", type=int, default=N_BITS)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (FP32 vs MFMA) and autograd measurements")
+    ap.add_argument("--streamed", type=int, default=0, metavar="N",
+                    help="instead of the default workload, time the streamed path on an int64 planted "
+                         "signal of 2^N entries held in pinned host memory (10 <= N <= 32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -60,6 +95,10 @@ def main():
 
     import paper_1607_01039_amd as F
     import synth
+
+    if args.streamed:
+        print(json.dumps(bench_streamed(F, torch, np, synth, args.streamed)), flush=True)
+        return
 
     n = args.n
     N = 1 << n
@@ -145,7 +184,8 @@ def main():
         "config": {"workload": f"int32 WHT n={n} planted peak (seed {SEED}, p={P_NOISE}) + |W|>{THRESH} extraction",
                    "n": n, "elements": N, "threshold": THRESH, "schedule": F.get_schedule("int32", n)},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(dom_name)},
         "passes": per_pass,
         "pct_hbm_peak_per_pass_avg": round(100 * (len(pass_ms) * bytes_per_launch / (sum(
             float(np.mean(v)) for v in pass_ms.values()) / 1e3) / 1e9) / HBM_PEAK_GBS, 2),
@@ -234,6 +274,41 @@ def bench_batched(F, torch, np, synth):
     del flushbuf, outs, ref, x
     torch.cuda.empty_cache()
     return res
+
+
+def bench_streamed(F, torch, np, synth, n):
+    """Planted int64 signal of 2^n entries (seed 3, p = 0.48) in pinned host
+    memory, transformed by the streamed Kronecker path with the threshold
+    T = ceil(6 * 2^(n/2)) fused; wall time of the (synchronous) call, the
+    host link's pinned copy rates for reference, and the recovery checks."""
+    import math
+    N = 1 << n
+    T = int(math.ceil(6 * 2 ** (n / 2)))
+    log(f"[bench] streamed: allocating {N * 8 / 2**30:.0f} GiB pinned host memory")
+    t = torch.empty(N, dtype=torch.int64, pin_memory=True)
+    log("[bench] streamed: generating")
+    _, s, err = synth.planted(n, 3, 0.48, dtype=np.int64, out=t.numpy())
+    log("[bench] streamed: transforming")
+    t0 = time.perf_counter()
+    hits = F.fwht_int_(t, threshold=T, cap=1 << 16)
+    sec = time.perf_counter() - t0
+    log(f"[bench] streamed: {sec:.3f} s, {hits.count} hits")
+    # link ceiling: 1 GiB pinned copies each way, from a buffer of its own
+    h = torch.empty(1 << 27, dtype=torch.int64, pin_memory=True)
+    d = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    rates = {}
+    for name, dst, src in (("h2d", d, h), ("d2h", h, d)):
+        dst.copy_(src); torch.cuda.synchronize()
+        t1 = time.perf_counter(); dst.copy_(src); torch.cuda.synchronize()
+        rates[name] = round((1 << 30) / (time.perf_counter() - t1) / 1e9, 2)
+    gi, gv = hits.sorted()
+    ok = s in set(gi.tolist()) and int(t[s]) == N - 2 * err
+    link_bytes = 4 * N * 8
+    return {"metric": "streamed FWHT GElem/s (int64, pinned host, fused |W|>T extraction)",
+            "value": round(N / sec / 1e9, 4), "unit": "GElem/s", "seconds": round(sec, 3), "n": n,
+            "bytes_over_link": link_bytes, "link_GBs_effective": round(link_bytes / sec / 1e9, 2),
+            "pinned_copy_GBs": rates,
+            "threshold": T, "hits": hits.count, "planted_mask_recovered": bool(ok)}
 
 
 def bench_autograd(F, torch, np, synth):

@@ -23,7 +23,7 @@ TABLE = os.path.join(PKG, "tune", "gfx950.txt")
 
 # Compiled variants (must match csrc/fwht_variants_*.hip).
 CONTIG = {"int32": (12, 13, 14, 15), "float32": (12, 13, 14, 15), "int64": (11, 12, 13, 14)}
-SEGMENT_BITS = {"int32": (5, 6, 7), "float32": (5, 6, 7), "int64": (4, 5, 6)}
+SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
 MAX_TILE_BYTES = 128 * 1024
 RMAX = 9
 

@@ -97,7 +97,8 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
 // to the library, or $FWHT_TUNE_TABLE) when it has (dtype, n); otherwise the
 // fewest passes: one contiguous pass of up to 2^15 (int64: 2^13) entries,
 // then strided passes of at most 9 bits, balanced, each with a variant whose
-// tile height equals its bit count and whose rows are 256-byte segments.
+// tile height equals its bit count and whose row segments are the widest
+// (up to 1 KiB) that fit the tile.
 std::string default_schedule(int dtype, int n)
 {
     const std::string *tuned = tuned_schedule(dtype, n);
@@ -105,7 +106,10 @@ std::string default_schedule(int dtype, int n)
     const bool wide = dtype == FWHT_I64;
     const int cmax = wide ? 13 : 15;
     const int rmax = 9;
-    const int cb = wide ? 5 : 6;
+    // Widest row segment (up to 1 KiB) whose tile of 2^(cb + r) entries
+    // still fits the 128 KiB tile limit: wide segments keep strided passes
+    // close to contiguous ones in HBM efficiency.
+    const int tbmax = wide ? 14 : 15, cbmax = wide ? 7 : 8;
     if (n <= 12) return wide && n <= 11 ? "C11" : "C12";
     if (n <= cmax) return "C" + std::to_string(n);
     int P = 1;
@@ -118,6 +122,7 @@ std::string default_schedule(int dtype, int n)
     std::string out = "C" + std::to_string(c);
     for (int i = 0; i < ns; ++i) {
         const int r = s / ns + (i < s % ns ? 1 : 0);
+        const int cb = tbmax - r < cbmax ? tbmax - r : cbmax;
         out += ",S" + std::to_string(cb + r) + "c" + std::to_string(cb) + ":" + std::to_string(r);
     }
     return out;
@@ -227,15 +232,17 @@ int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi,
 int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, const Epilogue &epi, hipStream_t s)
 {
     if (nbits <= 0) return FWHT_OK;
-    const int cb = dtype == FWHT_I64 ? 5 : 6;
+    const int tbmax = dtype == FWHT_I64 ? 14 : 15, cbmax = dtype == FWHT_I64 ? 7 : 8;
     const int np = (nbits + 8) / 9;
     int done = lo;
     for (int i = 0; i < np; ++i) {
         const int r = nbits / np + (i < nbits % np ? 1 : 0);
-        const int c = r == 1 ? cb + 1 : cb;
-        const std::string name = "S" + std::to_string(c + r) + "c" + std::to_string(c);
-        const Variant *v = find_variant(dtype, name);
-        if (!v) return fail(FWHT_E_UNSUPPORTED, "no variant %s", name.c_str());
+        // the widest row segment that fits the tile and lies below bit `done`
+        int c = tbmax - r < cbmax ? tbmax - r : cbmax;
+        if (c > done) c = done;
+        const Variant *v = nullptr;
+        for (; c >= 4 && !v; --c) v = find_variant(dtype, "S" + std::to_string(c + r) + "c" + std::to_string(c));
+        if (!v) return fail(FWHT_E_UNSUPPORTED, "no strided variant for %d bits at bit %d", r, done);
         if (done < v->CB) return fail(FWHT_E_INVAL, "strided range starts below the row segment");
         PassArgs a{};
         a.total = total;

@@ -38,6 +38,13 @@ std::vector<Variant> variants_u32()
         Variant{"S13c7", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, false>},
         Variant{"S14c7", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, false>},
         Variant{"S15c7", 15, 7, 1024, false, &launch_tile<15, 7, 1024, false, S, false>},
+        Variant{"S9c8", 9, 8, 64, false, &launch_tile<9, 8, 64, false, S, false>},
+        Variant{"S10c8", 10, 8, 64, false, &launch_tile<10, 8, 64, false, S, false>},
+        Variant{"S11c8", 11, 8, 128, false, &launch_tile<11, 8, 128, false, S, false>},
+        Variant{"S12c8", 12, 8, 256, false, &launch_tile<12, 8, 256, false, S, false>},
+        Variant{"S13c8", 13, 8, 512, false, &launch_tile<13, 8, 512, false, S, false>},
+        Variant{"S14c8", 14, 8, 512, false, &launch_tile<14, 8, 512, false, S, false>},
+        Variant{"S15c8", 15, 8, 1024, false, &launch_tile<15, 8, 1024, false, S, false>},
     };
 }
 

@@ -38,6 +38,13 @@ std::vector<Variant> variants_u64()
         Variant{"S12c6", 12, 6, 256, false, &launch_tile<12, 6, 256, false, S, false>},
         Variant{"S13c6", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, false>},
         Variant{"S14c6", 14, 6, 512, false, &launch_tile<14, 6, 512, false, S, false>},
+        Variant{"S8c7", 8, 7, 64, false, &launch_tile<8, 7, 64, false, S, false>},
+        Variant{"S9c7", 9, 7, 64, false, &launch_tile<9, 7, 64, false, S, false>},
+        Variant{"S10c7", 10, 7, 64, false, &launch_tile<10, 7, 64, false, S, false>},
+        Variant{"S11c7", 11, 7, 128, false, &launch_tile<11, 7, 128, false, S, false>},
+        Variant{"S12c7", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, false>},
+        Variant{"S13c7", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, false>},
+        Variant{"S14c7", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, false>},
     };
 }
 

@@ -251,7 +251,13 @@ struct BatchedKernel {
 #pragma unroll
             for (int j = 0; j < E; ++j) v[j] *= sc;
         }
-        dispatch_store<MM>(a, I, v, lane, wave, cur);
+        // Opaque copies of the thread coordinates: the store addresses are
+        // then recomputed here instead of being kept live (and spilled) from
+        // the loads.
+        uint32_t slane = lane, swave = wave;
+        asm volatile("" : "+v"(slane));
+        asm volatile("" : "+s"(swave));
+        dispatch_store<MM>(a, I, v, slane, swave, cur);
     }
 
     // Transform sizes are a run-time property of each tile; the item code is
@@ -290,8 +296,14 @@ struct BatchedKernel {
         __shared__ S lds[LDS_ELEMS];
         __shared__ int32_t s_item;
         const uint32_t t = threadIdx.x;
-        for (int32_t it = fetch(a, &s_item, t); it < a.nitems; it = fetch(a, &s_item, t))
-            item_any(a, read_item(a, it), lds, t);
+        for (int32_t it = fetch(a, &s_item, t); it < a.nitems; it = fetch(a, &s_item, t)) {
+            // An opaque copy of the thread id per item: the per-layout lane,
+            // wave and LDS offsets derived from it are recomputed for each
+            // item rather than hoisted out of the loop and kept live.
+            uint32_t tt = t;
+            asm volatile("" : "+v"(tt));
+            item_any(a, read_item(a, it), lds, tt);
+        }
     }
 };
 

@@ -71,9 +71,8 @@ __device__ __forceinline__ uint16_t to_half_bits<FWHT_PREC_FP16_MFMA>(float x)
 template <>
 __device__ __forceinline__ uint16_t to_half_bits<FWHT_PREC_BF16_MFMA>(float x)
 {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
-    return (uint16_t)(u >> 16);
+    const __bf16 h = (__bf16)x;  // round to nearest even (gfx950 converts in hardware)
+    return __builtin_bit_cast(uint16_t, h);
 }
 
 template <int PREC>
@@ -318,11 +317,17 @@ struct BatchedMfmaKernel {
         if (a.normalize) sc *= (float)(1.0 / sqrt((double)(1ull << MM)));
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] *= sc;
+        // Opaque copies of the thread coordinates: the store addresses are
+        // then recomputed here instead of being kept live (and spilled) from
+        // the loads.
+        uint32_t slane = lane, swave = wave;
+        asm volatile("" : "+v"(slane));
+        asm volatile("" : "+s"(swave));
         if constexpr (needB) {
-            transpose_bc(reinterpret_cast<float *>(lds), v, lane, wave);
-            store_vec<2, MM>(a, I, v, lane, wave);
+            transpose_bc(reinterpret_cast<float *>(lds), v, slane, swave);
+            store_vec<2, MM>(a, I, v, slane, swave);
         } else {
-            store_vec<0, MM>(a, I, v, lane, wave);
+            store_vec<0, MM>(a, I, v, slane, swave);
         }
     }
 
@@ -333,9 +338,14 @@ struct BatchedMfmaKernel {
         const uint32_t t = threadIdx.x;
         for (int32_t it = Base::fetch(a, &s_item, t); it < a.nitems; it = Base::fetch(a, &s_item, t)) {
             const BItem I = Base::read_item(a, it);
+            // An opaque copy of the thread id per item: the per-layout lane,
+            // wave and LDS offsets derived from it are recomputed for each
+            // item rather than hoisted out of the loop and kept live.
+            uint32_t tt = t;
+            asm volatile("" : "+v"(tt));
             static_for<2, TB + 1>([&](auto M0) {
                 constexpr int MM = decltype(M0)::value;
-                if (I.m == MM) item<MM>(a, I, lds, t);
+                if (I.m == MM) item<MM>(a, I, lds, tt);
             });
         }
     }

@@ -124,7 +124,7 @@ __device__ __forceinline__ uint32_t pdep_rt(uint32_t x)
 // ------------------------------------------------------------------ pass args
 struct PassArgs {
     uint64_t total;      // entries in the array (batch * 2^n)
-    uint64_t colblocks;  // 2^(b - CB): column blocks per row
+    uint64_t colblocks;  // 2^(b - CB): column blocks per row (a power of two)
     uint64_t ntiles;     // tiles in this pass
     uint32_t b;          // log2 of the row stride
     uint32_t act;        // transformed tile bits
@@ -143,15 +143,21 @@ struct PassArgs {
     // uses it to report positions in the whole array
     uint32_t kshift, kL;
     uint64_t kbase;
+    // destination of the pass (nullptr: in place); same layout as the source
+    void *dst;
 };
 
 template <class S> struct Arith;
 template <> struct Arith<uint32_t> {
+    // |v| <= 2^31 fits 32 bits, so the comparison is done in 32 bits against
+    // T clamped to [0, 2^32 - 1] (T >= 2^31 then matches nothing; T < 0
+    // matches everything).
     __device__ static bool above(uint32_t v, const PassArgs &a)
     {
-        int32_t s = (int32_t)v;
-        uint32_t mag = s < 0 ? 0u - v : v;
-        return a.T < 0 || (int64_t)mag > a.T;
+        const int32_t s = (int32_t)v;
+        const uint32_t mag = s < 0 ? 0u - v : v;
+        const uint32_t t32 = a.T < 0 ? 0u : a.T > 0xffffffffll ? 0xffffffffu : (uint32_t)a.T;
+        return a.T < 0 || mag > t32;
     }
 };
 template <> struct Arith<uint64_t> {
@@ -330,6 +336,42 @@ struct TileKernel {
         return ok;
     }
 
+    // Threshold epilogue, in two parts around the final stores from layout M
+    // (element j goes to global entry wb + lb/sizeof(S) + goff(pdep(j, M))).
+    // Before the stores: bit j of the mask is set when element j is a hit
+    // (one compare per element).  After them, and only in a wave where some
+    // lane has a hit (rare for thresholds in the noise tail): a uniform loop
+    // over the elements re-reads each hit from the entry this thread has just
+    // written and appends it, so no register array stays live for it.
+    template <uint32_t M, bool FULLT>
+    __device__ static __forceinline__ uint32_t tile_hit_mask(const S (&v)[E], uint64_t wb, uint32_t lb,
+                                                             const PassArgs &a)
+    {
+        static_assert(E <= 32, "hit mask holds 32 elements");
+        const uint64_t lo = wb + lb / sizeof(S);
+        uint32_t hm = 0;
+        static_for<0, E>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            const bool in = FULLT || lo + goff(cpdep((uint32_t)j, M), a.b) < a.total;
+            hm |= (uint32_t)(in && Arith<S>::above(v[j], a)) << j;
+        });
+        return hm;
+    }
+    template <uint32_t M>
+    __device__ static __forceinline__ void emit_tile_hits(const S *buf, uint32_t hm, uint64_t wb, uint32_t lb,
+                                                          const PassArgs &a)
+    {
+        if (__ballot(hm != 0) == 0) return;
+        const uint64_t lo = wb + lb / sizeof(S);
+#pragma unroll 1
+        for (int j = 0; j < E; ++j) {
+            const bool hit = (hm >> j) & 1u;
+            const uint64_t off = lo + goff(pdep_rt<M>((uint32_t)j), a.b);
+            const S val = hit ? buf[off] : S(0);
+            emit_hits<S>(hit, off, val, a);
+        }
+    }
+
     template <bool FULLT>
     __device__ static __forceinline__ void load_vec(const S *__restrict__ buf, S (&v)[E], uint32_t lane,
                                                     uint32_t wave, uint64_t base, const PassArgs &a)
@@ -368,18 +410,13 @@ struct TileKernel {
         constexpr uint32_t M0 = LS.m[0];
         const uint32_t lb = lane_bytes<M0>(lane, a.b);
         const uint64_t wb = base + wave_off<M0>(wave, a.b);
+        uint32_t hm = 0;
+        if constexpr (TH) hm = tile_hit_mask<M0, FULLT>(v, wb, lb, a);
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
             S *p = buf + (wb + goff(jp, a.b));
             const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
-            if constexpr (TH) {
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const bool in = FULLT || off + e < a.total;
-                    emit_hits<S>(in && Arith<S>::above(v[jt * VEC + e], a), off + e, v[jt * VEC + e], a);
-                }
-            }
             v4u q;
             S *qs = reinterpret_cast<S *>(&q);
 #pragma unroll
@@ -394,6 +431,7 @@ struct TileKernel {
                     if (off + e < a.total) buf[off + e] = v[jt * VEC + e];
             }
         });
+        if constexpr (TH) emit_tile_hits<M0>(buf, hm, wb, lb, a);
     }
 
     template <int P, bool FULLT>
@@ -403,21 +441,20 @@ struct TileKernel {
         constexpr uint32_t M = LS.m[P];
         const uint32_t lb = lane_bytes<M>(lane, a.b);
         const uint64_t wb = base + wave_off<M>(wave, a.b);
+        uint32_t hm = 0;
+        if constexpr (TH) hm = tile_hit_mask<M, FULLT>(v, wb, lb, a);
         static_for<0, E>([&](auto J) {
             constexpr int j = decltype(J)::value;
             constexpr uint32_t jp = cpdep((uint32_t)j, M);
             S *p = buf + (wb + goff(jp, a.b));
             if (FULLT) {
-                if constexpr (TH)
-                    emit_hits<S>(Arith<S>::above(v[j], a), (uint64_t)(p - buf) + lb / sizeof(S), v[j], a);
                 gstore1<NTM>(reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb), v[j]);
             } else {
                 const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
-                const bool in = off < a.total;
-                if constexpr (TH) emit_hits<S>(in && Arith<S>::above(v[j], a), off, v[j], a);
-                if (in) buf[off] = v[j];
+                if (off < a.total) buf[off] = v[j];
             }
         });
+        if constexpr (TH) emit_tile_hits<M>(buf, hm, wb, lb, a);
     }
 
     template <bool FULLT>
@@ -433,7 +470,7 @@ struct TileKernel {
     }
 
     template <bool FULLT>
-    __device__ static __forceinline__ void tile_body(S *__restrict__ buf, S *lds, uint32_t t, uint64_t base,
+    __device__ static __forceinline__ void tile_body(const S *buf, S *out, S *lds, uint32_t t, uint64_t base,
                                                      const PassArgs &a)
     {
         const uint32_t lane = t & 63u;
@@ -469,22 +506,34 @@ struct TileKernel {
                 for (int j = 0; j < E; ++j) v[j] *= a.scale;
             }
         }
-        if (cur == 0) store_vec<FULLT>(buf, v, lane, wave, base, a);
-        else dispatch_store<FULLT>(buf, v, lane, wave, base, a, cur);
+        // The store addresses repeat the load addresses; an opaque copy of
+        // the lane id makes the compiler recompute them here instead of
+        // keeping 64-bit load addresses live (and spilled) across the tile.
+        uint32_t slane = lane;
+        asm volatile("" : "+v"(slane));
+        if (cur == 0) store_vec<FULLT>(out, v, slane, wave, base, a);
+        else dispatch_store<FULLT>(out, v, slane, wave, base, a, cur);
         if (wrote) __syncthreads();  // the next tile reuses the LDS buffer
     }
 
     __device__ static __forceinline__ void run(S *__restrict__ buf, const PassArgs &a)
     {
         __shared__ S lds[LDS_ELEMS];
+        S *out = a.dst ? static_cast<S *>(a.dst) : buf;
         const uint32_t t = threadIdx.x;
         const uint32_t b = COLS ? (uint32_t)CB : a.b;
+        const uint32_t cbl = (uint32_t)__builtin_ctzll(a.colblocks);  // colblocks = 2^cbl
         for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-            const uint64_t g = tile / a.colblocks;
-            const uint64_t cb = tile - g * a.colblocks;
+            const uint64_t g = tile >> cbl;
+            const uint64_t cb = tile & (a.colblocks - 1);
             const uint64_t base = ((g << R) << b) + (cb << CB);
-            if ((((g + 1) << R) << b) <= a.total) tile_body<true>(buf, lds, t, base, a);
-            else tile_body<false>(buf, lds, t, base, a);
+            // An opaque copy of the row-stride exponent: every element's
+            // offset depends on it, and without this the compiler hoists all
+            // of them out of the tile loop and spills them.
+            PassArgs at = a;
+            asm volatile("" : "+s"(at.b));
+            if ((((g + 1) << R) << b) <= a.total) tile_body<true>(buf, out, lds, t, base, at);
+            else tile_body<false>(buf, out, lds, t, base, at);
         }
     }
 };

@@ -94,7 +94,7 @@ def test_streamed_planted_n32(F, O):
     import torch
     n = 32
     T = int(np.ceil(6 * 2 ** (n / 2)))
-    t = torch.empty(1 << n, dtype=torch.int64).pin_memory()
+    t = torch.empty(1 << n, dtype=torch.int64, pin_memory=True)
     x, s, err = synth.planted(n, 3, 0.48, dtype=np.int64, out=t.numpy())
     d = t.cuda()
     hits = F.fwht_int_(t, threshold=T, cap=1 << 16)
