@@ -22,7 +22,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tune", "gfx950.txt")
 
 # Compiled variants (must match csrc/fwht_variants_*.hip).
-CONTIG = {"int32": (12, 13, 14, 15), "float32": (12, 13, 14, 15), "int64": (11, 12, 13, 14)}
+CONTIG = {"int32": (12, 13, 14, 15, 16), "float32": (12, 13, 14, 15, 16), "int64": (11, 12, 13, 14)}
 SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
 MAX_TILE_BYTES = 128 * 1024
 RMAX = 9
@@ -50,13 +50,18 @@ def compositions(s: int, k: int, lo: int = 1, hi: int = RMAX):
             yield (first,) + rest
 
 
+def first_passes(dtype: str, n: int):
+    """Contiguous first passes for n bits: C16 only with strided passes after it."""
+    return [c for c in CONTIG[dtype] if c <= n and (c < 16 or n > c)]
+
+
 def candidates(dtype: str, n: int, max_cands: int = 400):
-    cmax = max(CONTIG[dtype])
-    if n <= cmax:
+    single = max(c for c in CONTIG[dtype] if c < 16)
+    if n <= single:
         return [f"C{max(min(CONTIG[dtype]), n)}"]
-    best_p = min(1 + -(-(n - c) // RMAX) for c in CONTIG[dtype] if c <= n)
+    best_p = min(1 + -(-(n - c) // RMAX) for c in first_passes(dtype, n))
     out = []
-    for c in CONTIG[dtype]:
+    for c in first_passes(dtype, n):
         s = n - c
         ns = best_p - 1
         if ns < 1 or s > ns * RMAX or s < ns:

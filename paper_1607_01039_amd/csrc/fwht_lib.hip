@@ -86,6 +86,12 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
         int r = want < 0 ? cap : want;
         if (r < 1 || r > cap) { why = "bit count out of range for " + tok; return false; }
         if (r > n - done) r = n - done;
+        // the 2^16-entry contiguous variant transforms exactly its 16 bits and
+        // carries no epilogue, so strided passes must follow it
+        if (v->cols && v->TB == 16 && (r != 16 || done + r >= n)) {
+            why = "C16 covers exactly 16 bits and must be followed by strided passes";
+            return false;
+        }
         out.push_back(Pass{v, done, r});
         done += r;
     }

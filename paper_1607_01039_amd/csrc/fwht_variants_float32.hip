@@ -3,6 +3,7 @@
 // strided pass over tiles of 2^(TB-CB) rows x 2^CB contiguous columns, so it
 // transforms up to TB-CB index bits per pass.
 #include "fwht_internal.hpp"
+#include "wht_contig16.hpp"
 #include "wht_tile.hpp"
 
 namespace fwht {
@@ -15,6 +16,7 @@ std::vector<Variant> variants_f32()
         Variant{"C13", 13, 6, 512, true, &launch_tile<13, 6, 512, true, S, false>},
         Variant{"C14", 14, 6, 512, true, &launch_tile<14, 6, 512, true, S, false>},
         Variant{"C15", 15, 6, 1024, true, &launch_tile<15, 6, 1024, true, S, false>},
+        Variant{"C16", 16, 6, 1024, true, &launch_contig16<S>},
         Variant{"S8c5", 8, 5, 64, false, &launch_tile<8, 5, 64, false, S, false>},
         Variant{"S9c5", 9, 5, 64, false, &launch_tile<9, 5, 64, false, S, false>},
         Variant{"S10c5", 10, 5, 64, false, &launch_tile<10, 5, 64, false, S, false>},

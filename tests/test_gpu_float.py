@@ -80,7 +80,9 @@ def _float_variant_cases():
         return [("unbuilt", 0, "")]
     cases = []
     for v in vs:
-        if v.startswith("C"):
+        if v == "C16":  # only as a first pass over exactly 16 bits
+            cases.append((v, 20, "C16,S12c8:4"))
+        elif v.startswith("C"):
             cases.append((v, int(v[1:]), v))
         else:
             tb, cb = (int(x) for x in v[1:].split("c"))

@@ -75,7 +75,10 @@ def _variant_cases(dtype):
     import paper_1607_01039_amd as F
     cases = []
     for v in F.list_variants(dtype):
-        if v.startswith("C"):
+        if v == "C16":  # only as a first pass over exactly 16 bits
+            cases.append((v, 20, "C16,S12c8:4"))
+            cases.append((v, 17, "C16,S9c8:1"))
+        elif v.startswith("C"):
             tb = int(v[1:])
             cases.append((v, tb, v))
             cases.append((v, tb - 3, v))
