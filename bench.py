@@ -41,7 +41,7 @@ THRESH = 6 * (1 << 15)
 # valid only for the kernel sources they were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_int32_n30.txt")
 KERNEL_SOURCES = tuple("paper_1607_01039_amd/csrc/" + f for f in (
-    "wht_tile.hpp", "wht_contig16.hpp", "wht_batched.hpp", "fwht_variants_int32.hip"))
+    "wht_tile.hpp", "wht_contig16.hpp", "fwht_variants_int32.hip"))
 
 
 def kernel_source_hash():

@@ -33,34 +33,14 @@ struct BArgs {
     int32_t *queue;  // [1] next item
 };
 
-// Layouts of a 2^TB tile with K register bits per thread, the top tile bit
-// pinned as a register bit in all of them: L0 = low VB bits + top K - VB bits;
-// then ascending groups of K - 1 untransformed bits, each + the pinned bit,
-// the last topped up with the highest other bits.
-constexpr LayoutList make_pinned_layouts(int TB, int K, int VB)
+// The work list and the segment table are read-only during a launch; reading
+// them through the constant address space lets the compiler use scalar loads
+// for wave-uniform indices (vector loads, each waited for before the data
+// access that needs its result, serialised the per-item address arithmetic).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *as_const(const T *p)
 {
-    LayoutList L{};
-    const uint32_t full = lowmask(TB);
-    const uint32_t pin = 1u << (TB - 1);
-    const int top = K - VB;
-    L.m[0] = lowmask(VB) | (lowmask(top) << (TB - top));
-    L.fresh[0] = L.m[0];
-    L.n = 1;
-    uint32_t rem = full & ~L.m[0];
-    while (rem) {
-        uint32_t g = 0;
-        int c = 0;
-        for (int b = 0; b < TB && c < K - 1; ++b)
-            if ((rem >> b) & 1u) { g |= 1u << b; ++c; }
-        rem &= ~g;
-        L.fresh[L.n] = g;
-        g |= pin;
-        ++c;
-        for (int b = TB - 2; b >= 0 && c < K; --b)
-            if (!((g >> b) & 1u)) { g |= 1u << b; ++c; }
-        L.m[L.n++] = g;
-    }
-    return L;
+    return (const __attribute__((address_space(4))) T *)p;
 }
 
 template <int TB, int NT>
@@ -76,23 +56,28 @@ struct BatchedKernel {
     static constexpr int LDS_ELEMS = (1 << (TB - 1)) + (1 << (TB - 1)) / 32;
     static_assert(LS.n <= 8, "too many layouts");
 
-    // Entries of tile index idx = (register part jp) | (wave part wp) |
-    // (lane part lp) for transforms of size 2^MM: a pointer to the entry, or
-    // null for an empty slot.  When every lane bit lies below MM the segment
-    // (and so the base address) is uniform across the wave.
+    // Entry of tile index idx = (register part jp) | (wave part wp) | (lane
+    // part lp) for transforms of size 2^MM.  `ok` is false for an empty slot
+    // (past the tile's last transform); the pointer is then an entry of the
+    // tile's first transform, so that it is always safe to load (the caller
+    // discards the value) and the address needs no branch: the segment-table
+    // reads of neighbouring entries stay shared.  When every lane bit lies
+    // below MM the segment (and so the base address) is uniform.
     template <int MM, uint32_t LANEMASK>
-    __device__ static __forceinline__ S *addr(const BArgs &a, const BItem &I, uint32_t jp, uint32_t wp, uint32_t lp)
+    __device__ static __forceinline__ S *addr(const BArgs &a, const BItem &I, uint32_t jp, uint32_t wp, uint32_t lp,
+                                              bool &ok)
     {
         if constexpr ((LANEMASK >> MM) == 0) {
-            const uint32_t q = __builtin_amdgcn_readfirstlane((jp | wp) >> MM);
-            if ((int32_t)q >= I.nseg) return nullptr;
-            S *base = a.data + a.segs[I.seg0 + q] + ((jp | wp) & lowmask(MM));
-            return base + lp;
+            const uint32_t q = (jp | wp) >> MM;  // uniform: wp comes from the wave id
+            ok = (int32_t)q < I.nseg;
+            const uint32_t qc = ok ? q : 0u;
+            return a.data + as_const(a.segs)[I.seg0 + qc] + ((jp | wp) & lowmask(MM)) + lp;
         } else {
             const uint32_t idx = jp | wp | lp;
             const uint32_t q = idx >> MM;
-            if ((int32_t)q >= I.nseg) return nullptr;
-            return a.data + a.segs[I.seg0 + q] + (idx & lowmask(MM));
+            ok = (int32_t)q < I.nseg;
+            const uint32_t qc = ok ? q : 0u;
+            return a.data + a.segs[I.seg0 + qc] + (idx & lowmask(MM));
         }
     }
 
@@ -165,9 +150,10 @@ struct BatchedKernel {
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
-            const S *p = addr<MM, Split<0>::LANE>(a, I, jp, wp, lp);
-            v4u q = {0u, 0u, 0u, 0u};
-            if (p) q = *reinterpret_cast<const v4u *>(p);
+            bool ok;
+            const S *p = addr<MM, Split<0>::LANE>(a, I, jp, wp, lp, ok);
+            v4u q = *reinterpret_cast<const v4u *>(p);
+            if (!ok) q = v4u{0u, 0u, 0u, 0u};
             const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -185,19 +171,21 @@ struct BatchedKernel {
             static_for<0, E / VEC>([&](auto JT) {
                 constexpr int jt = decltype(JT)::value;
                 constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M);
-                S *p = addr<MM, Split<0>::LANE>(a, I, jp, wp, lp);
+                bool ok;
+                S *p = addr<MM, Split<0>::LANE>(a, I, jp, wp, lp, ok);
                 v4u q;
                 S *qs = reinterpret_cast<S *>(&q);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
-                if (p) *reinterpret_cast<v4u *>(p) = q;
+                if (ok) *reinterpret_cast<v4u *>(p) = q;
             });
         } else {
             static_for<0, E>([&](auto J) {
                 constexpr int j = decltype(J)::value;
                 constexpr uint32_t jp = cpdep((uint32_t)j, M);
-                S *p = addr<MM, Split<P>::LANE>(a, I, jp, wp, lp);
-                if (p) *p = v[j];
+                bool ok;
+                S *p = addr<MM, Split<P>::LANE>(a, I, jp, wp, lp, ok);
+                if (ok) *p = v[j];
             });
         }
     }
@@ -246,7 +234,9 @@ struct BatchedKernel {
             dispatch_transpose(lds, v, t, cur, 0);
             cur = 0;
         }
-        if (a.normalize) {
+        int32_t nz = a.normalize;  // opaque copy: keeps the per-size scales out of the loop prologue
+        asm volatile("" : "+s"(nz));
+        if (nz) {
             const float sc = (float)(1.0 / sqrt((double)(1ull << MM)));
 #pragma unroll
             for (int j = 0; j < E; ++j) v[j] *= sc;
@@ -284,10 +274,12 @@ struct BatchedKernel {
 
     __device__ static __forceinline__ BItem read_item(const BArgs &a, int32_t it)
     {
-        BItem I = a.items[it];
-        I.m = __builtin_amdgcn_readfirstlane(I.m);
-        I.seg0 = __builtin_amdgcn_readfirstlane(I.seg0);
-        I.nseg = __builtin_amdgcn_readfirstlane(I.nseg);
+        const __attribute__((address_space(4))) BItem *ip = as_const(a.items) + it;
+        BItem I;
+        I.m = __builtin_amdgcn_readfirstlane(ip->m);
+        I.seg0 = __builtin_amdgcn_readfirstlane(ip->seg0);
+        I.nseg = __builtin_amdgcn_readfirstlane(ip->nseg);
+        I.pad = 0;
         return I;
     }
 

@@ -30,6 +30,10 @@
 #pragma once
 #include "wht_batched.hpp"
 
+#ifndef MFMA_GROUP_BLOCKS
+#define MFMA_GROUP_BLOCKS 4
+#endif
+
 namespace fwht {
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
@@ -106,8 +110,10 @@ struct MfmaOp<FWHT_PREC_BF16_MFMA> {
 
 template <int PREC>
 struct BatchedMfmaKernel {
+    static constexpr int MFMA_GROUP = MFMA_GROUP_BLOCKS;
     static constexpr int TB = 16, NT = 1024, E = 64, VEC = 4;
-    static constexpr int LDS_HALFS = (1 << TB) + (1 << TB) / 32;
+    // f16/bf16 tile with 4 halves of padding per 64 (see transpose_ab)
+    static constexpr int LDS_HALFS = (1 << TB) + 4 * ((1 << TB) / 64);
     using Base = BatchedKernel<16, 1024>;  // address, fetch and item helpers
 
     template <int WHICH>
@@ -129,20 +135,29 @@ struct BatchedMfmaKernel {
         return r;
     }
 
+    // Padding of the 16-bit tile: 4 halves (8 bytes) after every 64.  The
+    // four MA values of tile bits 0, 1 stay one aligned 8-byte store, and the
+    // 32 words one MB read touches (lanes on tile bits 0, 1, 4, 5, 6, 7) fall
+    // in 32 distinct banks: bits 6, 7 shift them by 2 and 4 words.  (Padding
+    // by one half per 32 misaligned those stores and gave 3-way conflicts.)
+    // The map is linear over disjoint bit sets, so thread and register parts
+    // are padded separately and added.
+    __device__ static __forceinline__ constexpr uint32_t hpad(uint32_t i) { return i + 4u * (i >> 6); }
+
     // MA -> MB through LDS in the operand format (see the file comment).
     __device__ static __forceinline__ void transpose_ab(uint16_t *lds, float (&v)[E], uint32_t lane, uint32_t wave)
     {
-        const uint32_t ta = lds_pad(lane_part<0>(lane) | wave_part<0>(wave));
-        const uint32_t tb = lds_pad(lane_part<1>(lane) | wave_part<1>(wave));
+        const uint32_t ta = hpad(lane_part<0>(lane) | wave_part<0>(wave));
+        const uint32_t tb = hpad(lane_part<1>(lane) | wave_part<1>(wave));
         __syncthreads();
         static_for<0, E>([&](auto J) {
             constexpr uint32_t jp = xl_reg_part(XL_A, decltype(J)::value);
-            lds[ta + jp + (jp >> 5)] = to_half_bits<PREC>(v[decltype(J)::value]);
+            lds[ta + hpad(jp)] = to_half_bits<PREC>(v[decltype(J)::value]);
         });
         __syncthreads();
         static_for<0, E>([&](auto J) {
             constexpr uint32_t jp = xl_reg_part(XL_B, decltype(J)::value);
-            v[decltype(J)::value] = from_half_bits(lds[tb + jp + (jp >> 5)]);
+            v[decltype(J)::value] = from_half_bits(lds[tb + hpad(jp)]);
         });
     }
 
@@ -150,23 +165,31 @@ struct BatchedMfmaKernel {
     // at a time; the half-tile index drops bit 11.
     __device__ static __forceinline__ uint32_t drop11(uint32_t i) { return (i & 0x7ffu) | ((i >> 1) & ~0x7ffu); }
 
+    // Bank swizzle of the FP32 half tile (no padding): bits 5, 6, 7 of the
+    // index are XORed into bits 1; 0 and 2; 3.  An MB store from 32 lanes
+    // (tile bits 0, 1, 4, 6, 7) and an MC load from 32 lanes (tile bits 2 .. 6)
+    // then each touch 32 distinct banks.  The map is linear over GF(2), so the
+    // thread and register parts are swizzled separately and XORed.
+    __device__ static __forceinline__ constexpr uint32_t swz(uint32_t q)
+    {
+        return q ^ (((q >> 5) & 1u) << 1) ^ (((q >> 6) & 1u) * 5u) ^ (((q >> 7) & 1u) << 3);
+    }
+
     __device__ static __forceinline__ void transpose_bc(float *lds, float (&v)[E], uint32_t lane, uint32_t wave)
     {
-        const uint32_t tb = lds_pad(drop11(lane_part<1>(lane) | wave_part<1>(wave)));
-        const uint32_t tc = lds_pad(drop11(lane_part<2>(lane) | wave_part<2>(wave)));
+        const uint32_t tb = swz(drop11(lane_part<1>(lane) | wave_part<1>(wave)));
+        const uint32_t tc = swz(drop11(lane_part<2>(lane) | wave_part<2>(wave)));
         static_for<0, 2>([&](auto H0) {
             constexpr int H = decltype(H0)::value;
             __syncthreads();
             static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
                 constexpr uint32_t jp = xl_reg_part(XL_B, decltype(J)::value);
-                constexpr uint32_t jq = (jp & 0x7ffu) | ((jp >> 1) & ~0x7ffu);
-                lds[tb + jq + (jq >> 5)] = v[decltype(J)::value];
+                lds[tb ^ swz(drop11(jp))] = v[decltype(J)::value];
             });
             __syncthreads();
             static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
                 constexpr uint32_t jp = xl_reg_part(XL_C, decltype(J)::value);
-                constexpr uint32_t jq = (jp & 0x7ffu) | ((jp >> 1) & ~0x7ffu);
-                v[decltype(J)::value] = lds[tc + jq + (jq >> 5)];
+                v[decltype(J)::value] = lds[tc ^ swz(drop11(jp))];
             });
         });
     }
@@ -226,8 +249,9 @@ struct BatchedMfmaKernel {
                 }
                 a[i] = to_half_bits<PREC>(val);
             }
-            // E/4 independent 16x16 blocks: register indices 2 and up.  The
-            // scheduling fences keep one block's operands live at a time.
+            // E/4 independent 16x16 blocks: register indices 2 and up.  A
+            // scheduling fence after every MFMA_GROUP blocks bounds the
+            // operands in flight while letting that many products overlap.
 #pragma unroll
             for (int blk = 0; blk < E / 4; ++blk) {
                 uint16_t b[4];
@@ -236,7 +260,7 @@ struct BatchedMfmaKernel {
                 const float4_t d = MfmaOp<PREC>::run(a, b);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[(blk << 2) | i] = d[i];
-                __builtin_amdgcn_sched_barrier(0);
+                if ((blk % MFMA_GROUP) == MFMA_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
             }
             return sh;
         }
@@ -251,9 +275,10 @@ struct BatchedMfmaKernel {
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = xl_reg_part(XL_A, (uint32_t)(jt << 2));
-            const float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
-            v4u q = {0u, 0u, 0u, 0u};
-            if (p) q = *reinterpret_cast<const v4u *>(p);
+            bool ok;
+            const float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp, ok);
+            v4u q = *reinterpret_cast<const v4u *>(p);
+            if (!ok) q = v4u{0u, 0u, 0u, 0u};
             const float *qs = reinterpret_cast<const float *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -273,12 +298,13 @@ struct BatchedMfmaKernel {
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = xl_reg_part(L, (uint32_t)(jt << 2));
-            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
+            bool ok;
+            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp, ok);
             v4u q;
             float *qs = reinterpret_cast<float *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
-            if (p) *reinterpret_cast<v4u *>(p) = q;
+            if (ok) *reinterpret_cast<v4u *>(p) = q;
         });
     }
 
@@ -292,8 +318,9 @@ struct BatchedMfmaKernel {
         static_for<0, E>([&](auto J) {
             constexpr int j = decltype(J)::value;
             constexpr uint32_t jp = xl_reg_part(L, (uint32_t)j);
-            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp);
-            if (p) *p = v[j];
+            bool ok;
+            float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp, ok);
+            if (ok) *p = v[j];
         });
     }
 
@@ -314,7 +341,11 @@ struct BatchedMfmaKernel {
         }
         // Undo the stage scales; 2^(-m/2) when normalising.
         float sc = (float)(1u << shift);
-        if (a.normalize) sc *= (float)(1.0 / sqrt((double)(1ull << MM)));
+        // an opaque copy of the flag, so that the scale of every size is not
+        // precomputed for the whole persistent loop (15 live registers)
+        int32_t nz = a.normalize;
+        asm volatile("" : "+s"(nz));
+        if (nz) sc *= (float)(1.0 / sqrt((double)(1ull << MM)));
 #pragma unroll
         for (int j = 0; j < E; ++j) v[j] *= sc;
         // Opaque copies of the thread coordinates: the store addresses are

@@ -13,7 +13,7 @@
 // time.  Like every pass, the butterflies on distinct bits commute (the
 // regrouping of Fig. 2 and Fig. 3).
 #pragma once
-#include "wht_batched.hpp"
+#include "wht_tile.hpp"
 
 namespace fwht {
 

@@ -101,6 +101,36 @@ constexpr bool lanes_contiguous(uint32_t m, int nlanebits)
     return (m & lowmask(nlanebits)) == 0;
 }
 
+// Layouts of a 2^TB tile with K register bits per thread, the top tile bit
+// pinned as a register bit in all of them: L0 = low VB bits + top K - VB bits;
+// then ascending groups of K - 1 untransformed bits, each + the pinned bit,
+// the last topped up with the highest other bits.
+constexpr LayoutList make_pinned_layouts(int TB, int K, int VB)
+{
+    LayoutList L{};
+    const uint32_t full = lowmask(TB);
+    const uint32_t pin = 1u << (TB - 1);
+    const int top = K - VB;
+    L.m[0] = lowmask(VB) | (lowmask(top) << (TB - top));
+    L.fresh[0] = L.m[0];
+    L.n = 1;
+    uint32_t rem = full & ~L.m[0];
+    while (rem) {
+        uint32_t g = 0;
+        int c = 0;
+        for (int b = 0; b < TB && c < K - 1; ++b)
+            if ((rem >> b) & 1u) { g |= 1u << b; ++c; }
+        rem &= ~g;
+        L.fresh[L.n] = g;
+        g |= pin;
+        ++c;
+        for (int b = TB - 2; b >= 0 && c < K; --b)
+            if (!((g >> b) & 1u)) { g |= 1u << b; ++c; }
+        L.m[L.n++] = g;
+    }
+    return L;
+}
+
 template <int I, int N, class F>
 __device__ __forceinline__ void static_for(F &&f)
 {
@@ -532,8 +562,10 @@ struct TileKernel {
             // of them out of the tile loop and spills them.
             PassArgs at = a;
             asm volatile("" : "+s"(at.b));
-            if ((((g + 1) << R) << b) <= a.total) tile_body<true>(buf, out, lds, t, base, at);
-            else tile_body<false>(buf, out, lds, t, base, at);
+            uint32_t tt = t;  // likewise for the offsets derived from the thread id
+            asm volatile("" : "+v"(tt));
+            if ((((g + 1) << R) << b) <= a.total) tile_body<true>(buf, out, lds, tt, base, at);
+            else tile_body<false>(buf, out, lds, tt, base, at);
         }
     }
 };
