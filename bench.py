@@ -111,8 +111,10 @@ def main():
     buf = torch.empty_like(src)
     log(f"[bench] s={s} errors={err} W(s)={peak_expect}")
 
+    hit_bufs = F.hit_buffers(buf, 1 << 16)
+
     def step():
-        return F.fwht_int_(buf, threshold=THRESH, cap=1 << 16, sync=False)
+        return F.fwht_int_(buf, threshold=THRESH, sync=False, hits=hit_bufs)
 
     def check(bufs):
         hits = F._collect(*bufs, 1 << 16)

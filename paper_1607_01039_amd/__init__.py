@@ -28,7 +28,7 @@ from ._lib import FWHTError
 PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
               "bf16": _lib.FWHT_PREC_BF16_MFMA}
 
-__all__ = ["fwht_int_", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
+__all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
            "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
            "FWHTError", "PRECISIONS"]
 
@@ -69,11 +69,19 @@ class Hits:
 
 
 def _thresh_buffers(dtype, cap, device):
+    """(idx, val, count) output buffers of a threshold request; the library
+    clears the count itself, so nothing is initialised here."""
     torch = _torch()
-    idx = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
-    val = torch.zeros(max(cap, 1), dtype=dtype, device=device)
-    cnt = torch.zeros(1, dtype=torch.int64, device=device)
+    idx = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+    val = torch.empty(max(cap, 1), dtype=dtype, device=device)
+    cnt = torch.empty(1, dtype=torch.int64, device=device)
     return idx, val, cnt
+
+
+def hit_buffers(t, cap: int = 1 << 16):
+    """Reusable output buffers for ``fwht_int_(t, threshold=..., hits=...)``
+    (a call that passes them allocates nothing)."""
+    return _thresh_buffers(t.dtype, cap, t.device)
 
 
 def _collect(idx, val, cnt, cap) -> Hits:
@@ -82,12 +90,14 @@ def _collect(idx, val, cnt, cap) -> Hits:
     return Hits(idx[:k].cpu().numpy().view(np.uint64).astype(np.int64), val[:k].cpu().numpy(), count, cap)
 
 
-def fwht_int_(t, threshold=None, cap: int = 1 << 16, sync: bool = True):
+def fwht_int_(t, threshold=None, cap: int = 1 << 16, sync: bool = True, hits=None):
     """In-place unnormalised integer WHT of a 1-D int32 / int64 tensor of 2^n entries.
 
     With ``threshold=T`` the last pass also collects every (k, W_k) with
     |W_k| > T; returns a ``Hits`` (after a stream sync when ``sync``), else
-    None.  A pinned host int64 tensor runs the streamed path synchronously.
+    the (idx, val, count) buffers.  ``hits`` may pass buffers from
+    ``hit_buffers`` (device tensors; their capacity replaces ``cap``).  A
+    pinned host int64 tensor runs the streamed path synchronously.
     """
     torch = _torch()
     if t.dim() != 1 or not t.is_contiguous():
@@ -101,7 +111,12 @@ def fwht_int_(t, threshold=None, cap: int = 1 << 16, sync: bool = True):
     bufs = None
     if threshold is not None:
         device = t.device if t.is_cuda else "cpu"
-        if t.is_cuda:
+        if hits is not None:
+            if not t.is_cuda:
+                raise ValueError("hits buffers are for device tensors")
+            bufs = hits
+            cap = int(hits[0].numel())
+        elif t.is_cuda:
             bufs = _thresh_buffers(t.dtype, cap, device)
         else:
             bufs = tuple(b.pin_memory() for b in _thresh_buffers(t.dtype, cap, "cpu"))

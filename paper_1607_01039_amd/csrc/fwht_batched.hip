@@ -14,12 +14,6 @@
 
 namespace fwht {
 
-// Zero the work-list counter (a kernel node, not a memset node, in the graph).
-__global__ void batched_reset_kernel(int32_t *p, int32_t n)
-{
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
 __global__ void __launch_bounds__(BATCH_NT, 1) batched_kernel(BArgs a)
 {
     BatchedKernel<BATCH_TB, BATCH_NT>::run(a);
@@ -39,8 +33,6 @@ struct Plan {
     // device state
     BItem *items = nullptr;
     int64_t *segs = nullptr;
-    int32_t *counters = nullptr;  // [0] work-list counter
-    int32_t ncounters = 0;
     int32_t nitems = 0;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -64,7 +56,6 @@ void release(Plan &p)
     if (p.graph) (void)hipGraphDestroy(p.graph);
     if (p.items) (void)hipFree(p.items);
     if (p.segs) (void)hipFree(p.segs);
-    if (p.counters) (void)hipFree(p.counters);
     p = Plan{};
 }
 
@@ -112,10 +103,8 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
     std::vector<int64_t> segs;
     build_items(off, lg, count, items, segs);
     p.nitems = (int32_t)items.size();
-    p.ncounters = 1;
     hipError_t e = hipMalloc(&p.items, sizeof(BItem) * items.size());
     if (e == hipSuccess) e = hipMalloc(&p.segs, sizeof(int64_t) * segs.size());
-    if (e == hipSuccess) e = hipMalloc(&p.counters, sizeof(int32_t) * (size_t)p.ncounters);
     if (e != hipSuccess) return fail(FWHT_E_NOMEM, "batched plan: %s", hipGetErrorString(e));
     e = hipMemcpy(p.items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p.segs, segs.data(), sizeof(int64_t) * segs.size(), hipMemcpyHostToDevice);
@@ -124,6 +113,7 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
     int grid = 0;
     int rc = grid_size(prec, &grid);
     if (rc) return rc;
+    if (grid > p.nitems) grid = p.nitems;
     if (!g_capture) {
         e = hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "capture stream");
@@ -134,14 +124,11 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
     a.segs = p.segs;
     a.nitems = p.nitems;
     a.normalize = normalize;
-    a.queue = p.counters;
-    // The graph: a small kernel clears the counters (no memset node), then
-    // the persistent kernel drains the work list.
+    // The graph: the persistent kernel alone (work is assigned statically,
+    // so there is no counter to reset between replays).
     e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
-    hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(256), 0, g_capture, p.counters, p.ncounters);
-    hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = launch_batched(prec, a, grid, g_capture);
+    const hipError_t le = launch_batched(prec, a, grid, g_capture);
     e = hipStreamEndCapture(g_capture, &p.graph);
     if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
     if (e != hipSuccess) return hip_fail(e, "end capture");

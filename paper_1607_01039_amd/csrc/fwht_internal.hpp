@@ -41,6 +41,7 @@ struct Epilogue {
     uint64_t *count = nullptr;
     uint32_t kshift = 0, kL = 0;  // hit-index remap (see PassArgs)
     uint64_t kbase = 0;
+    int clear_count = 0;  // run_passes clears *count before the first append
 };
 
 int fail(int code, const char *fmt, ...);

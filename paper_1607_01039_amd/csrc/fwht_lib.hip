@@ -204,6 +204,16 @@ int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi,
             a.ntiles = ((rows + (1ull << R) - 1) >> R) * a.colblocks;
         }
         const bool last = p + 1 == passes.size();
+        // the hit counter is cleared by the first of several passes (stream
+        // order puts that before the last pass's appends); a single pass
+        // needs a launch of its own for it
+        if (epi.thresh && epi.clear_count) {
+            if (p == 0 && !last) a.zero_first = (unsigned long long *)epi.count;
+            if (p == 0 && last) {
+                const int rc = zero_count(epi.count, s);
+                if (rc) return rc;
+            }
+        }
         if (last) {
             a.kshift = epi.kshift;
             a.kL = epi.kL;
@@ -386,8 +396,7 @@ int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream
         epi.val = th->val;
         epi.cap = th->cap;
         epi.count = th->count;
-        rc = zero_count(th->count, s);
-        if (rc) return rc;
+        epi.clear_count = 1;
         if (n == 0) return fwht_threshold(data, dtype, 0, th, stream);
     }
     return run_passes(data, dtype, n, 1, epi, s);

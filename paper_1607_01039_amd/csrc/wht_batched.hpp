@@ -1,11 +1,12 @@
 // wht_batched.hpp -- persistent kernel for many independent transforms of
 // uneven sizes (2^2 .. 2^16 entries each) in one launch.
 //
-// Work comes from a host-built list of tiles handed out through one atomic
-// counter, largest transforms first (the equal-load principle of section 3,
-// with longest-first order for the tail).  A tile is 2^16 entries: the
-// entries of 2^(16-m) transforms of one size 2^m, gathered from their own
-// offsets.  One workgroup transforms a whole tile, so no tile ever waits for
+// Work comes from a host-built list of tiles, largest transforms first.  A
+// tile is 2^16 entries: the entries of 2^(16-m) transforms of one size 2^m,
+// gathered from their own offsets, so every tile costs about the same and a
+// static cyclic assignment (workgroup g takes tiles g, g + G, g + 2G, ...)
+// balances the load (the equal-load principle of section 3) without a shared
+// counter.  One workgroup transforms a whole tile, so no tile ever waits for
 // another one: there is no communication between workgroups at all.
 //
 // The tile lives in registers (1024 threads x 64 entries).  Between layouts
@@ -30,7 +31,6 @@ struct BArgs {
     const int64_t *segs;
     int32_t nitems;
     int32_t normalize;
-    int32_t *queue;  // [1] next item
 };
 
 // The work list and the segment table are read-only during a launch; reading
@@ -261,17 +261,6 @@ struct BatchedKernel {
         });
     }
 
-    // Next item index for the whole block (uniform: it steers branches that
-    // contain barriers, so it travels through a scalar register).
-    __device__ static __forceinline__ int32_t fetch(const BArgs &a, int32_t *s_item, uint32_t t)
-    {
-        if (t == 0) *s_item = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int32_t it = __builtin_amdgcn_readfirstlane(*s_item);
-        __syncthreads();
-        return it;
-    }
-
     __device__ static __forceinline__ BItem read_item(const BArgs &a, int32_t it)
     {
         const __attribute__((address_space(4))) BItem *ip = as_const(a.items) + it;
@@ -286,9 +275,10 @@ struct BatchedKernel {
     __device__ static __forceinline__ void run(const BArgs &a)
     {
         __shared__ S lds[LDS_ELEMS];
-        __shared__ int32_t s_item;
         const uint32_t t = threadIdx.x;
-        for (int32_t it = fetch(a, &s_item, t); it < a.nitems; it = fetch(a, &s_item, t)) {
+        // static cyclic assignment; every transpose starts with a barrier, so
+        // one item's last LDS reads finish before the next item's writes
+        for (int32_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
             // An opaque copy of the thread id per item: the per-layout lane,
             // wave and LDS offsets derived from it are recomputed for each
             // item rather than hoisted out of the loop and kept live.

@@ -365,9 +365,9 @@ struct BatchedMfmaKernel {
     __device__ static __forceinline__ void run(const BArgs &a)
     {
         __shared__ uint16_t lds[LDS_HALFS];
-        __shared__ int32_t s_item;
         const uint32_t t = threadIdx.x;
-        for (int32_t it = Base::fetch(a, &s_item, t); it < a.nitems; it = Base::fetch(a, &s_item, t)) {
+        // static cyclic assignment; each transpose starts with a barrier
+        for (int32_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
             const BItem I = Base::read_item(a, it);
             // An opaque copy of the thread id per item: the per-layout lane,
             // wave and LDS offsets derived from it are recomputed for each

@@ -117,6 +117,7 @@ struct Contig16Kernel {
     {
         __shared__ S lds[LDS_ELEMS];
         S *out = a.dst ? static_cast<S *>(a.dst) : buf;
+        if (a.zero_first && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_first = 0ull;
         for (uint64_t tl = blockIdx.x; tl < a.ntiles; tl += gridDim.x) {
             uint32_t t = threadIdx.x;
             asm volatile("" : "+v"(t));

@@ -175,6 +175,10 @@ struct PassArgs {
     uint64_t kbase;
     // destination of the pass (nullptr: in place); same layout as the source
     void *dst;
+    // when set, the first workgroup clears this counter before anything else
+    // (the hit count of a threshold fused into a LATER pass of the same
+    // transform, so that it needs no launch of its own)
+    unsigned long long *zero_first;
 };
 
 template <class S> struct Arith;
@@ -551,6 +555,7 @@ struct TileKernel {
         __shared__ S lds[LDS_ELEMS];
         S *out = a.dst ? static_cast<S *>(a.dst) : buf;
         const uint32_t t = threadIdx.x;
+        if (a.zero_first && blockIdx.x == 0 && t == 0) *a.zero_first = 0ull;
         const uint32_t b = COLS ? (uint32_t)CB : a.b;
         const uint32_t cbl = (uint32_t)__builtin_ctzll(a.colblocks);  // colblocks = 2^cbl
         for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {

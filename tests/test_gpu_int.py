@@ -164,6 +164,36 @@ def test_fused_threshold_matches_oracle(F, O, n, p, seed, T):
         assert s in set(gi.tolist())
 
 
+@pytest.mark.parametrize("n", [12, 20, 30])
+def test_reused_hit_buffers(F, O, n):
+    """The library clears the hit count itself (inside the first of several
+    passes, or with a launch of its own for a single pass): the same output
+    buffers reused across calls, still holding the previous call's hits, give
+    each call exactly its own hits."""
+    import torch
+    x, s, err = synth.planted(n, 11 + n, 0.3)
+    T = (6 if n >= 30 else 4) << (n // 2)  # about 14 noise hits at n = 20, none expected at n = 30
+    src = _dev(x)
+    t = torch.empty_like(src)
+    bufs = F.hit_buffers(t, 1 << 12)
+    if n <= 20:
+        ridx, rval, rcnt = O.threshold(O.wht_fig1(x), T)
+    for rep in range(3):
+        t.copy_(src)
+        out = F.fwht_int_(t, threshold=T, sync=False, hits=bufs)
+        assert out is bufs
+        torch.cuda.synchronize()
+        hits = F._collect(*bufs, 1 << 12)
+        gi, gv = hits.sorted()
+        if n <= 20:
+            assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+        else:  # n = 30: the planted peak and its exact value; each hit checked by a direct sum
+            assert s in set(gi.tolist()) and int(gv[list(gi).index(s)]) == (1 << n) - 2 * err
+            if rep == 0:
+                ks = gi[:2].tolist()
+                assert np.array_equal(O.wht_def_at(x, ks), gv[:2].astype(np.int64))
+
+
 def test_fused_threshold_capacity_overflow(F, O):
     n = 12
     x = synth.signs(1 << n, 9)
