@@ -127,7 +127,8 @@ int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, 
  * of squares).  For transform t (layout as in fwht_batched, HOST offsets and
  * log2n), writes out[3t] = sum x^2, out[3t+1] = sum y^2 and
  * out[3t+2] = sum (y - r)^2 (0 when r is NULL).  x, y: device FP32; r: device
- * FP64 or NULL; out: device double[3 * count], overwritten. */
+ * FP64 or NULL; out: device double[3 * count], overwritten.  1 <= count <=
+ * 2^23 (FWHT_E_RANGE above). */
 int fwht_norms(const float *x, const float *y, const double *r, const int64_t *offsets,
                const int32_t *log2n, int32_t count, double *out, void *stream);
 

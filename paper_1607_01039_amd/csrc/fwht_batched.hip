@@ -43,11 +43,23 @@ std::list<Plan> g_plans;  // most recent first
 constexpr size_t kMaxPlans = 8;
 hipStream_t g_capture = nullptr;
 
-uint64_t fnv(const void *p, size_t n, uint64_t h)
+// Cache key of the host arrays: a multiply-xorshift hash over 8-byte words
+// (a byte-wise hash of 4096 offsets and sizes took tens of microseconds,
+// spent on the host before every replay).
+uint64_t hash_words(const void *p, size_t n, uint64_t h)
 {
     const unsigned char *c = (const unsigned char *)p;
-    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
-    return h;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        memcpy(&w, c + i, 8);
+        h = (h ^ w) * 0x9E3779B97F4A7C15ull;
+        h ^= h >> 29;
+    }
+    uint64_t w = 0;
+    memcpy(&w, c + i, n - i);
+    h = (h ^ w ^ (uint64_t)n) * 0x9E3779B97F4A7C15ull;
+    return h ^ (h >> 31);
 }
 
 void release(Plan &p)
@@ -151,8 +163,8 @@ hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s)
 int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec,
             hipStream_t s)
 {
-    uint64_t h = fnv(off, sizeof(int64_t) * (size_t)count, 0xcbf29ce484222325ull);
-    h = fnv(lg, sizeof(int32_t) * (size_t)count, h);
+    uint64_t h = hash_words(off, sizeof(int64_t) * (size_t)count, 0xcbf29ce484222325ull);
+    h = hash_words(lg, sizeof(int32_t) * (size_t)count, h);
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_plans.begin();
     for (; it != g_plans.end(); ++it)

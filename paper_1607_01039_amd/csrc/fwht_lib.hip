@@ -530,8 +530,12 @@ int fwht_copy(void *dst, const void *src, uint64_t bytes, void *stream)
     if (!dst || !src || (((uintptr_t)dst | (uintptr_t)src | bytes) & 15))
         return fail(FWHT_E_INVAL, "copy needs 16-byte aligned pointers and size");
     const uint64_t n16 = bytes / 16;
+    // one 16-byte vector per thread while the grid allows (measured the
+    // fastest streaming copy on this GPU: 6.2 TB/s against 4.8 with a
+    // grid-stride loop over a capped grid); the dispatch counts work-items
+    // in 32 bits, so beyond 2^31 vectors the kernel loops
     uint64_t grid = (n16 + 255) / 256;
-    if (grid > 256 * 64) grid = 256 * 64;
+    if (grid > (1ull << 31) / 256) grid = (1ull << 31) / 256;
     if (grid == 0) return FWHT_OK;
     hipLaunchKernelGGL(copy_kernel, dim3((uint32_t)grid), dim3(256), 0, (hipStream_t)stream,
                        (uint4 *)dst, (const uint4 *)src, n16);

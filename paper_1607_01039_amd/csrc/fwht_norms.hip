@@ -78,5 +78,7 @@ extern "C" int fwht_norms(const float *x, const float *y, const double *r, const
 {
     if (!x || !y || !offsets || !log2n || !out) return fwht::fail(FWHT_E_INVAL, "NULL argument");
     if (count < 1) return fwht::fail(FWHT_E_INVAL, "count must be >= 1");
+    // one workgroup of 256 per transform; the dispatch counts work-items in 32 bits
+    if (count > (1 << 23)) return fwht::fail(FWHT_E_RANGE, "count must be <= 2^23");
     return fwht::norms(x, y, r, offsets, log2n, count, out, (hipStream_t)stream);
 }

@@ -140,7 +140,8 @@ template <class S>
 hipError_t launch_contig16(void *buf, const PassArgs &a, hipStream_t s)
 {
     if (a.act != lowmask(16) || (a.total & lowmask(16)) || a.thresh) return hipErrorInvalidValue;
-    const uint64_t grid = a.ntiles < (1ull << 30) ? a.ntiles : (1ull << 30);
+    const uint64_t maxgrid = (1ull << 31) / 1024;  // work-items counted in 32 bits; grid-stride loop
+    const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
     hipLaunchKernelGGL(wht_contig16_kernel<S>, dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf, a);
     return hipGetLastError();
 }

@@ -589,7 +589,9 @@ template <int TB, int CB, int NT, bool COLS, class S, bool NTM>
 hipError_t launch_tile(void *buf, const PassArgs &a, hipStream_t s)
 {
     constexpr int MINW = 2;
-    const uint64_t maxgrid = 1ull << 30;
+    // The dispatch packet counts work-items in 32 bits; the tile loop is
+    // grid-stride, so a capped grid still covers every tile.
+    const uint64_t maxgrid = (1ull << 31) / NT;
     const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
     if (a.thresh)
         hipLaunchKernelGGL((wht_tile_kernel<TB, CB, NT, COLS, S, true, NTM, MINW>), dim3((uint32_t)grid), dim3(NT),

@@ -271,3 +271,16 @@ def test_config_n30_planted_sampled(F, O):
     assert s in set(gi.tolist())
     O.wht_fig2_inplace(x, 4)
     assert np.array_equal(y, x)
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, 64 << 20])
+def test_copy_kernel(F, nbytes):
+    """The library's copy kernel (the bandwidth and counter calibration
+    reference) copies exactly, for a single vector, a ragged grid tail and
+    many blocks."""
+    import torch
+    src = _dev(synth.ints(nbytes // 4, 77, -(1 << 30), 1 << 30, dtype=np.int32))
+    dst = torch.zeros_like(src)
+    F.copy_(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
