@@ -26,6 +26,9 @@ CONTIG = {"int32": (12, 13, 14, 15, 16), "float32": (12, 13, 14, 15, 16), "int64
 SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
 MAX_TILE_BYTES = 128 * 1024
 RMAX = 9
+# strided variants from this tile size up (and C16) also exist as twins with
+# non-temporal loads and stores, named with a trailing "n"
+NT_MIN_TB = {"int32": 13, "float32": 13, "int64": 12}
 
 
 def strided_variant(dtype: str, r: int, cb: int):
@@ -55,7 +58,7 @@ def first_passes(dtype: str, n: int):
     return [c for c in CONTIG[dtype] if c <= n and (c < 16 or n > c)]
 
 
-def candidates(dtype: str, n: int, max_cands: int = 400):
+def candidates(dtype: str, n: int, max_cands: int = 1000):
     single = max(c for c in CONTIG[dtype] if c < 16)
     if n <= single:
         return [f"C{max(min(CONTIG[dtype]), n)}"]
@@ -73,17 +76,31 @@ def candidates(dtype: str, n: int, max_cands: int = 400):
                 parts = [strided_variant(dtype, r, cb) for r, cb in zip(comp, cbs)]
                 if None in parts:
                     continue
-                out.append(",".join([f"C{c}"] + [f"{v}:{r}" for v, r in zip(parts, comp)]))
+                # cache policy of the first pass and of the strided passes,
+                # chosen independently
+                for nt_first, nt in itertools.product((False, True), repeat=2):
+                    first = f"C{c}n" if nt_first and c == 16 else f"C{c}"
+                    names = [v + "n" if nt and r + cb >= NT_MIN_TB[dtype] else v
+                             for v, r, cb in zip(parts, comp, cbs)]
+                    spec = ",".join([first] + [f"{v}:{r}" for v, r in zip(names, comp)])
+                    if spec not in out:
+                        out.append(spec)
     return out[:max_cands]
 
 
-def time_schedule(F, torch, buf, dtype, n, spec, reps=5):
+def time_schedule(F, torch, buf, dtype, n, spec, reps=5, src=None):
+    """Median device time of one transform under `spec`.  With `src`, the
+    input is restored from it (untimed) before every run, so each run starts
+    from freshly written data as a real call does (cache state matters: a pass
+    with non-temporal loads is slower on data that was just written)."""
     F.set_schedule(dtype, n, spec)
     run = (lambda: F.fwht_float_(buf)) if dtype == "float32" else (lambda: F.fwht_int_(buf))
     run()
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
+        if src is not None:
+            buf.copy_(src)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         run()
@@ -105,6 +122,7 @@ def tune(dtype: str, ns, min_total_bits: int = 0, log=print):
             buf = torch.randn((1 << (total_bits - n), 1 << n), device="cuda", dtype=tdt)
         else:
             buf = torch.randint(-1, 2, (1 << n,), device="cuda", dtype=tdt)
+        src = buf.clone()
         F.set_schedule(dtype, n, None)
         default = F.get_schedule(dtype, n)
         cands = candidates(dtype, n)
@@ -113,16 +131,16 @@ def tune(dtype: str, ns, min_total_bits: int = 0, log=print):
         best = None
         t0 = time.time()
         for spec in cands:
-            ms = time_schedule(F, torch, buf, dtype, n, spec)
+            ms = time_schedule(F, torch, buf, dtype, n, spec, src=src)
             if best is None or ms < best[1]:
                 best = (spec, ms)
         F.set_schedule(dtype, n, None)
-        ms_def = time_schedule(F, torch, buf, dtype, n, default) if len(cands) > 1 else best[1]
+        ms_def = time_schedule(F, torch, buf, dtype, n, default, src=src) if len(cands) > 1 else best[1]
         F.set_schedule(dtype, n, None)
         results[n] = best
         log(f"[tune] {dtype} n={n} total=2^{total_bits}: {len(cands)} schedules in {time.time() - t0:.1f}s; "
             f"best {best[0]} {best[1]:.4f} ms (default {default} {ms_def:.4f} ms)")
-        del buf
+        del buf, src
         torch.cuda.empty_cache()
     return results
 

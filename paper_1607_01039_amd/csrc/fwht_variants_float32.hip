@@ -47,6 +47,19 @@ std::vector<Variant> variants_f32()
         Variant{"S13c8", 13, 8, 512, false, &launch_tile<13, 8, 512, false, S, false>},
         Variant{"S14c8", 14, 8, 512, false, &launch_tile<14, 8, 512, false, S, false>},
         Variant{"S15c8", 15, 8, 1024, false, &launch_tile<15, 8, 1024, false, S, false>},
+        // twins with non-temporal loads and stores (the autotuner picks per size)
+        Variant{"C16n", 16, 6, 1024, true, &launch_contig16<S, NT_LOAD | NT_STORE>},
+        Variant{"S13c5n", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c5n", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c6n", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c6n", 14, 6, 512, false, &launch_tile<14, 6, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S15c6n", 15, 6, 1024, false, &launch_tile<15, 6, 1024, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c7n", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c7n", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S15c7n", 15, 7, 1024, false, &launch_tile<15, 7, 1024, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c8n", 13, 8, 512, false, &launch_tile<13, 8, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c8n", 14, 8, 512, false, &launch_tile<14, 8, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S15c8n", 15, 8, 1024, false, &launch_tile<15, 8, 1024, false, S, NT_LOAD | NT_STORE>},
     };
 }
 

@@ -45,6 +45,18 @@ std::vector<Variant> variants_u64()
         Variant{"S12c7", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, false>},
         Variant{"S13c7", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, false>},
         Variant{"S14c7", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, false>},
+        // twins with non-temporal loads and stores (the autotuner picks per size)
+        Variant{"S12c4n", 12, 4, 256, false, &launch_tile<12, 4, 256, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c4n", 13, 4, 512, false, &launch_tile<13, 4, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S12c5n", 12, 5, 256, false, &launch_tile<12, 5, 256, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c5n", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c5n", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S12c6n", 12, 6, 256, false, &launch_tile<12, 6, 256, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c6n", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c6n", 14, 6, 512, false, &launch_tile<14, 6, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S12c7n", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S13c7n", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c7n", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, NT_LOAD | NT_STORE>},
     };
 }
 

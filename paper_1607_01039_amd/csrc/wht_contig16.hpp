@@ -17,7 +17,7 @@
 
 namespace fwht {
 
-template <class S>
+template <class S, int NTM = 0>
 struct Contig16Kernel {
     static_assert(sizeof(S) == 4, "2^16 entries of 4 bytes fill half the register file");
     static constexpr int TB = 16, NT = 1024, E = (1 << TB) / NT, K = 6, VEC = 4, VB = 2;
@@ -81,7 +81,7 @@ struct Contig16Kernel {
             static_for<0, E / VEC>([&](auto JT) {
                 constexpr int jt = decltype(JT)::value;
                 constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
-                const v4u q = *reinterpret_cast<const v4u *>(src + (jp | wp) + lp);
+                const v4u q = gload16<(NTM & NT_LOAD) != 0>(src + (jp | wp) + lp);
                 const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -108,7 +108,7 @@ struct Contig16Kernel {
         const uint32_t wp = pdep_rt<Split<2>::WAVE>(swave);
         static_for<0, E>([&](auto J) {
             constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, LS.m[2]);
-            dst[(jp | wp) + lp] = v[decltype(J)::value];
+            gstore1<(NTM & NT_STORE) != 0>(dst + ((jp | wp) + lp), v[decltype(J)::value]);
         });
         __syncthreads();  // the next tile reuses the LDS buffer
     }
@@ -127,22 +127,22 @@ struct Contig16Kernel {
     }
 };
 
-template <class S>
+template <class S, int NTM>
 __global__ void __launch_bounds__(1024, 1) wht_contig16_kernel(S *__restrict__ buf, PassArgs a)
 {
-    Contig16Kernel<S>::run(buf, a);
+    Contig16Kernel<S, NTM>::run(buf, a);
 }
 
 // Host launcher: every tile is full (the planner only schedules this variant
 // as the first pass of a transform of at least 2^17 entries, over all 16
 // bits, and never with an epilogue).
-template <class S>
+template <class S, int NTM = 0>
 hipError_t launch_contig16(void *buf, const PassArgs &a, hipStream_t s)
 {
     if (a.act != lowmask(16) || (a.total & lowmask(16)) || a.thresh) return hipErrorInvalidValue;
     const uint64_t maxgrid = (1ull << 31) / 1024;  // work-items counted in 32 bits; grid-stride loop
     const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
-    hipLaunchKernelGGL(wht_contig16_kernel<S>, dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf, a);
+    hipLaunchKernelGGL((wht_contig16_kernel<S, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf, a);
     return hipGetLastError();
 }
 

@@ -279,7 +279,12 @@ __device__ __forceinline__ void gstore1(S *p, S x)
     else *p = x;
 }
 
-template <int TB, int CB, int NT, bool COLS, class S, bool TH, bool NTM>
+// Cache policy of a pass's global accesses (bit mask): non-temporal loads
+// and/or stores.  Measured on the strided passes, streaming accesses keep
+// the caches from holding lines that will not be reused before eviction.
+constexpr int NT_LOAD = 1, NT_STORE = 2;
+
+template <int TB, int CB, int NT, bool COLS, class S, bool TH, int NTM>
 struct TileKernel {
     static constexpr int E = (1 << TB) / NT;
     static constexpr int K = clog2(E);
@@ -418,14 +423,14 @@ struct TileKernel {
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
             const S *p = buf + (wb + goff(jp, a.b));
             if (FULLT) {
-                const v4u q = gload16<NTM>(reinterpret_cast<const char *>(p) + lb);
+                const v4u q = gload16<(NTM & NT_LOAD) != 0>(reinterpret_cast<const char *>(p) + lb);
                 const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
             } else {
                 const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
                 if (off + VEC <= a.total) {
-                    const v4u q = gload16<NTM>(buf + off);
+                    const v4u q = gload16<(NTM & NT_LOAD) != 0>(buf + off);
                     const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -456,9 +461,9 @@ struct TileKernel {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) qs[e] = v[jt * VEC + e];
             if (FULLT) {
-                gstore16<NTM>(reinterpret_cast<char *>(p) + lb, q);
+                gstore16<(NTM & NT_STORE) != 0>(reinterpret_cast<char *>(p) + lb, q);
             } else if (off + VEC <= a.total) {
-                gstore16<NTM>(buf + off, q);
+                gstore16<(NTM & NT_STORE) != 0>(buf + off, q);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -482,7 +487,7 @@ struct TileKernel {
             constexpr uint32_t jp = cpdep((uint32_t)j, M);
             S *p = buf + (wb + goff(jp, a.b));
             if (FULLT) {
-                gstore1<NTM>(reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb), v[j]);
+                gstore1<(NTM & NT_STORE) != 0>(reinterpret_cast<S *>(reinterpret_cast<char *>(p) + lb), v[j]);
             } else {
                 const uint64_t off = (uint64_t)(p - buf) + lb / sizeof(S);
                 if (off < a.total) buf[off] = v[j];
@@ -578,14 +583,14 @@ struct TileKernel {
 // Each variant is compiled to keep at least MINW waves per SIMD resident
 // (register budget 512 / MINW), so that several tiles share a CU and one
 // tile's LDS phases overlap another tile's HBM traffic.
-template <int TB, int CB, int NT, bool COLS, class S, bool TH, bool NTM, int MINW>
+template <int TB, int CB, int NT, bool COLS, class S, bool TH, int NTM, int MINW>
 __global__ void __launch_bounds__(NT, MINW) wht_tile_kernel(S *__restrict__ buf, PassArgs a)
 {
     TileKernel<TB, CB, NT, COLS, S, TH, NTM>::run(buf, a);
 }
 
 // Host-side launcher of one variant (threshold epilogue chosen per launch).
-template <int TB, int CB, int NT, bool COLS, class S, bool NTM>
+template <int TB, int CB, int NT, bool COLS, class S, int NTM>
 hipError_t launch_tile(void *buf, const PassArgs &a, hipStream_t s)
 {
     constexpr int MINW = 2;

@@ -80,12 +80,13 @@ def _float_variant_cases():
         return [("unbuilt", 0, "")]
     cases = []
     for v in vs:
-        if v == "C16":  # only as a first pass over exactly 16 bits
-            cases.append((v, 20, "C16,S12c8:4"))
+        base = v.rstrip("n")  # "n": twin with non-temporal loads and stores
+        if base == "C16":  # only as a first pass over exactly 16 bits
+            cases.append((v, 20, f"{v},S12c8:4"))
         elif v.startswith("C"):
-            cases.append((v, int(v[1:]), v))
+            cases.append((v, int(base[1:]), v))
         else:
-            tb, cb = (int(x) for x in v[1:].split("c"))
+            tb, cb = (int(x) for x in base[1:].split("c"))
             cases.append((v, 12 + tb - cb, f"C12,{v}:{tb - cb}"))
     return cases
 

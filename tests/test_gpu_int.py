@@ -75,15 +75,16 @@ def _variant_cases(dtype):
     import paper_1607_01039_amd as F
     cases = []
     for v in F.list_variants(dtype):
-        if v == "C16":  # only as a first pass over exactly 16 bits
-            cases.append((v, 20, "C16,S12c8:4"))
-            cases.append((v, 17, "C16,S9c8:1"))
+        base = v.rstrip("n")  # "n": twin with non-temporal loads and stores
+        if base == "C16":  # only as a first pass over exactly 16 bits
+            cases.append((v, 20, f"{v},S12c8:4"))
+            cases.append((v, 17, f"{v},S9c8:1"))
         elif v.startswith("C"):
-            tb = int(v[1:])
+            tb = int(base[1:])
             cases.append((v, tb, v))
             cases.append((v, tb - 3, v))
         else:
-            tb, cb = (int(x) for x in v[1:].split("c"))
+            tb, cb = (int(x) for x in base[1:].split("c"))
             R = tb - cb
             cases.append((v, 12 + R, f"C12,{v}:{R}"))
             if R > 1:
