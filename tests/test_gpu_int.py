@@ -285,3 +285,33 @@ def test_copy_kernel(F, nbytes):
     F.copy_(dst, src)
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
+
+
+@pytest.mark.parametrize("n", [33, 34])
+def test_int64_large_in_hbm(F, O, n):
+    """int64 up to the in-HBM limit (n = 34: 128 GiB resident), planted peak
+    (seed 3, p = 0.48), fused threshold T = ceil(6 * 2^(n/2)): the peak in
+    closed form, the definition at the peak, at a hit and at a random k, and
+    the involution H(Hx) = 2^n x checked on every entry."""
+    import math
+    import torch
+    N = 1 << n
+    T = int(math.ceil(6 * 2 ** (n / 2)))
+    x, s, err = synth.planted(n, 3, 0.48, dtype=np.int64)
+    t = torch.empty(N, dtype=torch.int64, device="cuda")
+    C = 1 << 28
+    for c0 in range(0, N, C):
+        t[c0:c0 + C].copy_(torch.from_numpy(x[c0:c0 + C]))
+    hits = F.fwht_int_(t, threshold=T, cap=1 << 12)
+    assert int(t[s].item()) == N - 2 * err
+    gi, gv = hits.sorted()
+    assert s in set(gi.tolist()) and hits.count <= (1 << 12)
+    other = [k for k in gi.tolist() if k != s][:1]
+    ks = [s] + other + [int(np.random.default_rng(n).integers(0, N))]
+    got = t[torch.tensor(ks, device="cuda")].cpu().numpy()
+    assert np.array_equal(O.wht_def_at(x, ks), got)
+    F.fwht_int_(t)
+    for c0 in range(0, N, C):
+        assert torch.equal(t[c0:c0 + C], torch.from_numpy(x[c0:c0 + C]).cuda() * N), c0
+    del t
+    torch.cuda.empty_cache()
