@@ -296,21 +296,31 @@ def bench_streamed(F, torch, np, synth, n):
     hits = F.fwht_int_(t, threshold=T, cap=1 << 16)
     sec = time.perf_counter() - t0
     log(f"[bench] streamed: {sec:.3f} s, {hits.count} hits")
-    # link ceiling: 1 GiB pinned copies each way, from a buffer of its own
-    h = torch.empty(1 << 27, dtype=torch.int64, pin_memory=True)
-    d = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    # link ceiling: 1 GiB pinned copies each way, from buffers of their own,
+    # one direction at a time and both at once on two streams
+    h, h2 = (torch.empty(1 << 27, dtype=torch.int64, pin_memory=True) for _ in range(2))
+    d, d2 = (torch.empty(1 << 27, dtype=torch.int64, device="cuda") for _ in range(2))
     rates = {}
-    for name, dst, src in (("h2d", d, h), ("d2h", h, d)):
+    for name, dst, src in (("h2d", d, h), ("d2h", h2, d2)):
         dst.copy_(src); torch.cuda.synchronize()
         t1 = time.perf_counter(); dst.copy_(src); torch.cuda.synchronize()
         rates[name] = round((1 << 30) / (time.perf_counter() - t1) / 1e9, 2)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    with torch.cuda.stream(s1):
+        d.copy_(h, non_blocking=True)
+    with torch.cuda.stream(s2):
+        h2.copy_(d2, non_blocking=True)
+    torch.cuda.synchronize()
+    rates["both"] = round(2 * (1 << 30) / (time.perf_counter() - t1) / 1e9, 2)
     gi, gv = hits.sorted()
     ok = s in set(gi.tolist()) and int(t[s]) == N - 2 * err
     link_bytes = 4 * N * 8
     return {"metric": "streamed FWHT GElem/s (int64, pinned host, fused |W|>T extraction)",
             "value": round(N / sec / 1e9, 4), "unit": "GElem/s", "seconds": round(sec, 3), "n": n,
             "bytes_over_link": link_bytes, "link_GBs_effective": round(link_bytes / sec / 1e9, 2),
-            "pinned_copy_GBs": rates,
+            "pinned_copy_GBs": rates, "link_frac_of_bidirectional": round(link_bytes / sec / 1e9 / rates["both"], 3),
             "threshold": T, "hits": hits.count, "planted_mask_recovered": bool(ok)}
 
 

@@ -39,7 +39,7 @@ def run_batched(F, x, off, lg, normalize=True, precision="fp32", reps=1):
 
 
 @pytest.mark.parametrize("count,lo,hi,seed", [(1, 16, 16, 1), (3, 2, 4, 2), (57, 2, 16, 3), (300, 8, 16, 4),
-                                              (40, 15, 16, 5), (200, 2, 9, 6)])
+                                              (40, 15, 16, 5), (200, 2, 9, 6), (20000, 2, 5, 9)])
 @pytest.mark.parametrize("normalize", [True, False])
 def test_batched_matches_oracle(F, O, count, lo, hi, seed, normalize):
     lg, off, tot = synth.ragged(count, lo, hi, seed)
@@ -121,7 +121,7 @@ def test_batched_rejects_bad_input(F):
 
 @pytest.mark.parametrize("precision,bound", [("fp16", 1e-3), ("bf16", 1e-2)])
 @pytest.mark.parametrize("count,lo,hi,seed", [(1, 16, 16, 1), (3, 2, 4, 2), (57, 2, 16, 3), (300, 8, 16, 4),
-                                              (40, 15, 16, 5)])
+                                              (40, 15, 16, 5), (20000, 2, 5, 9)])
 @pytest.mark.parametrize("normalize", [True, False])
 def test_batched_mfma_matches_oracle(F, O, precision, bound, count, lo, hi, seed, normalize):
     lg, off, tot = synth.ragged(count, lo, hi, seed)
