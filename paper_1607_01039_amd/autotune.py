@@ -23,7 +23,9 @@ TABLE = os.path.join(PKG, "tune", "gfx950.txt")
 
 # Compiled variants (must match csrc/fwht_variants_*.hip).
 CONTIG = {"int32": (12, 13, 14, 15, 16), "float32": (12, 13, 14, 15, 16), "int64": (11, 12, 13, 14)}
-SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
+SEGMENT_BITS = {"int32": (5, 6, 7, 8, 9), "float32": (5, 6, 7, 8, 9), "int64": (4, 5, 6, 7)}
+# 2^16-entry strided variants (4-byte types): column bits -> their (only) bit count
+PINNED16 = {7: 9, 8: 8, 9: 7}
 MAX_TILE_BYTES = 128 * 1024
 RMAX = 9
 # strided variants from this tile size up (and C16) also exist as twins with
@@ -31,9 +33,17 @@ RMAX = 9
 NT_MIN_TB = {"int32": 13, "float32": 13, "int64": 12}
 
 
+# row-segment widths compiled for the tile variants of up to 2^15 entries
+TILE_SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
+
+
 def strided_variant(dtype: str, r: int, cb: int):
     esz = 8 if dtype == "int64" else 4
     tb = cb + r
+    if tb == 16 and esz == 4:
+        return f"S16c{cb}" if PINNED16.get(cb) == r else None
+    if cb not in TILE_SEGMENT_BITS[dtype]:
+        return None
     if (1 << tb) * esz > MAX_TILE_BYTES:
         return None
     vec = 16 // esz

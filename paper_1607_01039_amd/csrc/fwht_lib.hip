@@ -92,6 +92,11 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
             why = "C16 covers exactly 16 bits and must be followed by strided passes";
             return false;
         }
+        // the 2^16-entry strided variants transform exactly their 16 - CB bits
+        if (!v->cols && v->TB == 16 && r != cap) {
+            why = "a 2^16-entry strided variant covers exactly its full height";
+            return false;
+        }
         out.push_back(Pass{v, done, r});
         done += r;
     }

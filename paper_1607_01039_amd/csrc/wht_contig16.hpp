@@ -1,32 +1,41 @@
-// wht_contig16.hpp -- contiguous pass over tiles of 2^16 consecutive 4-byte
-// entries (256 KiB), transformed over all 16 tile bits in one HBM round trip.
+// wht_contig16.hpp -- passes over tiles of 2^16 4-byte entries (256 KiB),
+// twice what LDS holds in one piece.
 //
-// The tile is twice what LDS holds, so it lives in registers (1024 threads x
-// 64 entries) and the top tile bit is a register bit in every layout
-// ("pinned"): each transpose through LDS moves one half of the tile at a time
-// (2^15 entries + padding), the half given by the pinned bit.  Layouts for 64
-// entries per thread:
-//   L0 {0, 1, 12, 13, 14, 15}: 16-byte vector loads (bits 0, 1 in a vector);
-//   L1 {2 .. 6, 15};  L2 {7 .. 11, 15}: lanes hold bits 0 .. 5, so a wave's
-//   stores cover 256 contiguous bytes.
-// All 16 bits are transformed, so the layout sequence is fixed at compile
-// time.  Like every pass, the butterflies on distinct bits commute (the
-// regrouping of Fig. 2 and Fig. 3).
+// The tile lives in registers (1024 threads x 64 entries) and the top tile
+// bit is a register bit in every layout ("pinned"): each transpose through LDS
+// moves one half of the tile at a time (2^15 entries + padding), the half
+// given by the pinned bit.
+//   * contiguous (CB = 0, "C16"): 2^16 consecutive entries, all 16 bits
+//     transformed; layouts L0 {0, 1, 12 .. 15} (16-byte loads), L1 {2 .. 6, 15},
+//     L2 {7 .. 11, 15}.
+//   * strided (CB > 0, "S16c<CB>"): 2^CB contiguous columns (2^CB * 4 bytes
+//     per row segment) of 2^(16 - CB) rows at a stride of 2^b entries; the
+//     16 - CB row bits are transformed.  L0 as above, then one layout with the
+//     remaining row bits (e.g. CB = 8: L1 {8 .. 11, 14, 15}).
+// In both, the lanes of the last layout hold tile bits 0 .. 5, so every wave
+// store covers 256 contiguous bytes.  Every candidate bit is transformed (the
+// planner uses these variants at their full height only), so the layout
+// sequence is fixed at compile time.  Like every pass, the butterflies on
+// distinct bits commute (the regrouping of Fig. 2 and Fig. 3).
 #pragma once
 #include "wht_tile.hpp"
 
 namespace fwht {
 
-template <class S, int NTM = 0>
-struct Contig16Kernel {
+template <class S, int CB, bool TH, int NTM>
+struct Pinned16Kernel {
     static_assert(sizeof(S) == 4, "2^16 entries of 4 bytes fill half the register file");
     static constexpr int TB = 16, NT = 1024, E = (1 << TB) / NT, K = 6, VEC = 4, VB = 2;
-    static constexpr LayoutList LS = make_pinned_layouts(TB, K, VB);
+    static constexpr bool COLS = CB == 0;
+    static constexpr int R = TB - CB;  // transformed bits
+    static constexpr LayoutList LS = make_pinned_layouts(TB, K, VB, CB);
+    static constexpr int LAST = LS.n - 1;
     static constexpr uint32_t FULL = lowmask(TB);
     static constexpr uint32_t HALF = lowmask(TB - 1);
     static constexpr int LDS_ELEMS = (1 << (TB - 1)) + (1 << (TB - 1)) / 32;
-    static_assert(LS.n == 3, "three layouts");
-    static_assert(lanes_contiguous(LS.m[2], 6), "last layout stores whole 256-byte runs");
+    static_assert(COLS ? LS.n == 3 : LS.n == 2, "layout count");
+    static_assert(lanes_contiguous(LS.m[LAST], 6), "last layout stores whole 256-byte runs");
+    static_assert(CB == 0 || CB >= VB + 5, "a wave's vector loads cover whole 512-byte row segments");
 
     template <int P>
     struct Split {
@@ -34,6 +43,15 @@ struct Contig16Kernel {
         static constexpr uint32_t LANE = low_set_bits(TM, 6);
         static constexpr uint32_t WAVE = TM & ~LANE;
     };
+
+    // Global offset (entries) of tile index idx: rows of stride 2^b above the
+    // CB column bits (the identity for a contiguous tile).  Linear over
+    // disjoint bit sets, so register, wave and lane parts add up.
+    __device__ static __forceinline__ uint64_t goff(uint32_t idx, uint32_t b)
+    {
+        if constexpr (COLS) return idx;
+        else return ((uint64_t)(idx >> CB) << b) + (idx & lowmask(CB));
+    }
 
     // Half H of the registers of layout P (those whose pinned bit is H) to
     // LDS, or back; the LDS index drops the pinned bit.
@@ -69,19 +87,45 @@ struct Contig16Kernel {
         from_lds<TO, 1>(lds, v, t);
     }
 
-    __device__ static __forceinline__ void tile(const S *src, S *dst, S *lds, uint32_t t, const PassArgs &a)
+    // Threshold epilogue around the final stores (as in the 2^15-entry tile
+    // pass): a 64-bit per-thread hit mask before the stores; after them, only
+    // in a wave with a hit, a uniform loop re-reads each hit from the entry
+    // this thread has just written and appends it.
+    __device__ static __forceinline__ uint64_t hit_mask(const S (&v)[E], const PassArgs &a)
+    {
+        uint64_t hm = 0;
+        static_for<0, E>([&](auto J) {
+            constexpr int j = decltype(J)::value;
+            hm |= (uint64_t)Arith<S>::above(v[j], a) << j;
+        });
+        return hm;
+    }
+    __device__ static __forceinline__ void emit(const S *buf, uint64_t hm, uint64_t lo, const PassArgs &a)
+    {
+        if (__ballot(hm != 0) == 0) return;
+#pragma unroll 1
+        for (int j = 0; j < E; ++j) {
+            const bool hit = (hm >> j) & 1u;
+            const uint64_t off = lo + goff(pdep_rt<LS.m[LAST]>((uint32_t)j), a.b);
+            const S val = hit ? buf[off] : S(0);
+            emit_hits<S>(hit, off, val, a);
+        }
+    }
+
+    __device__ static __forceinline__ void tile(const S *src, S *dst, S *lds, uint32_t t, uint64_t base,
+                                                const PassArgs &a)
     {
         const uint32_t lane = t & 63u;
         const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
         S v[E];
         {
             constexpr uint32_t M0 = LS.m[0];
-            const uint32_t lp = pdep_rt<Split<0>::LANE>(lane);
-            const uint32_t wp = pdep_rt<Split<0>::WAVE>(wave);
+            const uint64_t lb = goff(pdep_rt<Split<0>::LANE>(lane), a.b);
+            const uint64_t wb = base + goff(pdep_rt<Split<0>::WAVE>(wave), a.b);
             static_for<0, E / VEC>([&](auto JT) {
                 constexpr int jt = decltype(JT)::value;
                 constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
-                const v4u q = gload16<(NTM & NT_LOAD) != 0>(src + (jp | wp) + lp);
+                const v4u q = gload16<(NTM & NT_LOAD) != 0>(src + (wb + goff(jp, a.b)) + lb);
                 const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
@@ -90,9 +134,11 @@ struct Contig16Kernel {
         reg_stages<S, LS.m[0], LS.fresh[0], E>(v, FULL);
         transpose<0, 1>(lds, v, t);
         reg_stages<S, LS.m[1], LS.fresh[1], E>(v, FULL);
-        __syncthreads();
-        transpose<1, 2>(lds, v, t);
-        reg_stages<S, LS.m[2], LS.fresh[2], E>(v, FULL);
+        if constexpr (LS.n == 3) {
+            __syncthreads();
+            transpose<1, 2>(lds, v, t);
+            reg_stages<S, LS.m[2], LS.fresh[2], E>(v, FULL);
+        }
         if constexpr (std::is_same<S, float>::value) {
             if (a.do_scale) {
 #pragma unroll
@@ -104,12 +150,18 @@ struct Contig16Kernel {
         uint32_t slane = lane, swave = wave;
         asm volatile("" : "+v"(slane));
         asm volatile("" : "+s"(swave));
-        const uint32_t lp = pdep_rt<Split<2>::LANE>(slane);
-        const uint32_t wp = pdep_rt<Split<2>::WAVE>(swave);
+        // The lanes of the last layout are tile bits 0 .. 5 (column bits), so a
+        // store is a wave-uniform base plus the lane id as a 32-bit index.
+        static_assert(Split<LAST>::LANE == lowmask(6), "lanes on tile bits 0 .. 5");
+        const uint64_t wo = base + goff(pdep_rt<Split<LAST>::WAVE>(swave), a.b);
+        S *ub = dst + wo;
+        uint64_t hm = 0;
+        if constexpr (TH) hm = hit_mask(v, a);
         static_for<0, E>([&](auto J) {
-            constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, LS.m[2]);
-            gstore1<(NTM & NT_STORE) != 0>(dst + ((jp | wp) + lp), v[decltype(J)::value]);
+            constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, LS.m[LAST]);
+            gstore1<(NTM & NT_STORE) != 0>(ub + goff(jp, a.b) + slane, v[decltype(J)::value]);
         });
+        if constexpr (TH) emit(dst, hm, wo + slane, a);
         __syncthreads();  // the next tile reuses the LDS buffer
     }
 
@@ -118,32 +170,52 @@ struct Contig16Kernel {
         __shared__ S lds[LDS_ELEMS];
         S *out = a.dst ? static_cast<S *>(a.dst) : buf;
         if (a.zero_first && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_first = 0ull;
+        const uint32_t cbl = (uint32_t)__builtin_ctzll(a.colblocks);  // colblocks = 2^cbl
         for (uint64_t tl = blockIdx.x; tl < a.ntiles; tl += gridDim.x) {
+            // opaque copies per tile: the offsets derived from them are
+            // recomputed for each tile instead of being hoisted and kept live
             uint32_t t = threadIdx.x;
             asm volatile("" : "+v"(t));
-            const uint64_t base = tl << TB;
-            tile(buf + base, out + base, lds, t, a);
+            PassArgs at = a;
+            asm volatile("" : "+s"(at.b));
+            const uint64_t g = tl >> cbl, cb = tl & (a.colblocks - 1);
+            const uint64_t base = COLS ? (tl << TB) : (((g << R) << at.b) + (cb << CB));
+            tile(buf, out, lds, t, base, at);
         }
     }
 };
 
-template <class S, int NTM>
-__global__ void __launch_bounds__(1024, 1) wht_contig16_kernel(S *__restrict__ buf, PassArgs a)
+template <class S, int CB, bool TH, int NTM>
+__global__ void __launch_bounds__(1024, 1) wht_pinned16_kernel(S *__restrict__ buf, PassArgs a)
 {
-    Contig16Kernel<S, NTM>::run(buf, a);
+    Pinned16Kernel<S, CB, TH, NTM>::run(buf, a);
 }
 
-// Host launcher: every tile is full (the planner only schedules this variant
-// as the first pass of a transform of at least 2^17 entries, over all 16
-// bits, and never with an epilogue).
+// Host launchers.  Every tile is full: the planner schedules these variants
+// only over their full height, and the contiguous one only as the first pass
+// of a transform of at least 2^17 entries, with no epilogue.
+template <class S, int CB, int NTM>
+hipError_t launch_pinned16(void *buf, const PassArgs &a, hipStream_t s)
+{
+    constexpr int R = 16 - CB;
+    if (a.act != (lowmask(R) << CB)) return hipErrorInvalidValue;
+    if (CB == 0 && ((a.total & lowmask(16)) || a.thresh)) return hipErrorInvalidValue;
+    if (CB > 0 && (((a.total >> a.b) & lowmask(R)) || a.b < (uint32_t)CB)) return hipErrorInvalidValue;
+    const uint64_t maxgrid = (1ull << 31) / 1024;  // work-items counted in 32 bits; grid-stride loop
+    const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
+    if (a.thresh)
+        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, true, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf,
+                           a);
+    else
+        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, false, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf,
+                           a);
+    return hipGetLastError();
+}
+
 template <class S, int NTM = 0>
 hipError_t launch_contig16(void *buf, const PassArgs &a, hipStream_t s)
 {
-    if (a.act != lowmask(16) || (a.total & lowmask(16)) || a.thresh) return hipErrorInvalidValue;
-    const uint64_t maxgrid = (1ull << 31) / 1024;  // work-items counted in 32 bits; grid-stride loop
-    const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
-    hipLaunchKernelGGL((wht_contig16_kernel<S, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf, a);
-    return hipGetLastError();
+    return launch_pinned16<S, 0, NTM>(buf, a, s);
 }
 
 }  // namespace fwht

@@ -104,17 +104,18 @@ constexpr bool lanes_contiguous(uint32_t m, int nlanebits)
 // Layouts of a 2^TB tile with K register bits per thread, the top tile bit
 // pinned as a register bit in all of them: L0 = low VB bits + top K - VB bits;
 // then ascending groups of K - 1 untransformed bits, each + the pinned bit,
-// the last topped up with the highest other bits.
-constexpr LayoutList make_pinned_layouts(int TB, int K, int VB)
+// the last topped up with the highest other bits.  Only tile bits from LO up
+// are transformed (LO = CB for a strided tile whose low bits are columns).
+constexpr LayoutList make_pinned_layouts(int TB, int K, int VB, int LO = 0)
 {
     LayoutList L{};
-    const uint32_t full = lowmask(TB);
+    const uint32_t cand = lowmask(TB) & ~lowmask(LO);
     const uint32_t pin = 1u << (TB - 1);
     const int top = K - VB;
     L.m[0] = lowmask(VB) | (lowmask(top) << (TB - top));
-    L.fresh[0] = L.m[0];
+    L.fresh[0] = L.m[0] & cand;
     L.n = 1;
-    uint32_t rem = full & ~L.m[0];
+    uint32_t rem = cand & ~L.m[0];
     while (rem) {
         uint32_t g = 0;
         int c = 0;
