@@ -11,6 +11,9 @@ The arithmetic lives in ``wht_oracle.c`` (plain C, built with gcc into
 Functions follow section 2 (Eq. 2: y_i = sum_j (-1)^<i,j> x_j, natural order,
 unnormalised) and the algorithms of Fig. 1 (serial in-place butterflies),
 Fig. 2 (fork-join parallel decomposition) and Fig. 3 (external block scheme).
+Section 5.1's linear space reduction (the fold u_j = sum_{A i = j} x_i and
+the index map k' -> A^T k') is here too, with a plain GF(2) elimination
+(canonical basis, preimage of one reduced index) in Python.
 Integer results are wrap-around (mod 2^32 for int32 data, mod 2^64 for int64);
 floating point is IEEE double on the exactly up-cast input.
 """
@@ -83,6 +86,10 @@ class Oracle:
         L.wht_ragged_f64.argtypes = [_f64p, _i64p, _i32p, C.c_uint64, C.c_int]
         L.norms_f64.argtypes = [_f32p, _f32p, C.c_void_p, _i64p, _i32p, C.c_uint64,
                                 _f64p, _f64p, _f64p]
+        L.fold_u64.argtypes = [_u64p, C.c_int, _u64p, C.c_int, _u64p]
+        L.fold_u32.argtypes = [_u32p, C.c_int, _u64p, C.c_int, _u32p]
+        L.subspace_index.argtypes = [_u64p, C.c_int, C.c_uint64]
+        L.subspace_index.restype = C.c_uint64
 
     # ---- Eq. 2 written out ------------------------------------------------
     def wht_def(self, x: np.ndarray) -> np.ndarray:
@@ -225,6 +232,105 @@ class Oracle:
         """
         y = self.wht_batch(x, n, True)
         return self.wht_batch(2.0 * np.asarray(w, dtype=np.float64) * y, n, True)
+
+    # ---- section 5.1: linear space reduction --------------------------------
+    def fold(self, x: np.ndarray, rows, m: int) -> np.ndarray:
+        """u_j = sum_{i : A i = j} x_i for the map A with the given m rows
+        (bit t of A i is the parity of rows[t] & i); int32 or int64, wrapping."""
+        n = _log2(x.size)
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.uint64))
+        assert r.size == m
+        if x.dtype == np.int32:
+            u = np.empty(1 << m, dtype=np.uint32)
+            self._L.fold_u32(np.ascontiguousarray(x).view(np.uint32), n, r, m, u)
+            return u.view(np.int32)
+        if x.dtype == np.int64:
+            u = np.empty(1 << m, dtype=np.uint64)
+            self._L.fold_u64(np.ascontiguousarray(x).view(np.uint64), n, r, m, u)
+            return u.view(np.int64)
+        raise TypeError(x.dtype)
+
+    def subspace_index(self, rows, kp: int) -> int:
+        """A^T k' = XOR of rows[t] over the set bits t of k'."""
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.uint64))
+        return int(self._L.subspace_index(r, r.size, int(kp)))
+
+    def subspace_indices(self, rows, kps) -> np.ndarray:
+        return np.array([self.subspace_index(rows, k) for k in kps], dtype=np.uint64)
+
+
+# ---- GF(2) linear algebra for section 5.1 (plain Gaussian elimination) ------
+
+def gf2_rank(rows) -> int:
+    """Rank over GF(2) of the bit vectors `rows` (Python ints)."""
+    basis = []  # rows with distinct leading (highest) bits
+    for r in (int(v) for v in rows):
+        for b in basis:
+            r = min(r, r ^ b)
+        if r:
+            basis.append(r)
+            basis.sort(reverse=True)
+    return len(basis)
+
+
+def gf2_canonical_rows(rows, n: int):
+    """The unique reduced echelon basis of the row space of `rows` with
+    pivots at the lowest bits: row t has its lowest set bit p_t, p_0 < p_1 <
+    ..., and bit p_t is clear in every other row.  Returns a list of ints,
+    or None when the rows are linearly dependent."""
+    rs = [int(v) for v in rows]
+    m = len(rs)
+    if any(v >> n for v in rs):
+        raise ValueError("row has bits at or above n")
+    out = []
+    rest = list(rs)
+    for bit in range(n):
+        piv = next((v for v in rest if (v >> bit) & 1), None)
+        if piv is None:
+            continue
+        rest.remove(piv)
+        rest = [v ^ piv if (v >> bit) & 1 else v for v in rest]
+        out = [v ^ piv if (v >> bit) & 1 else v for v in out]
+        out.append(piv)
+    if len(out) < m:
+        return None
+    return sorted(out, key=lambda v: (v & -v))
+
+
+def fold_preimage(rows, n: int, j: int):
+    """Every i in [0, 2^n) with A i = j (bit t of A i is parity(rows[t] & i)),
+    by solving the linear system: one solution plus the span of the null
+    space.  Returns a sorted numpy uint64 array (2^(n - m) entries when A has
+    full rank m)."""
+    rs = [int(v) for v in rows]
+    m = len(rs)
+    # augmented system over the n unknown bits of i: rows[t] . i = bit t of j
+    eqs = [(rs[t], (j >> t) & 1) for t in range(m)]
+    pivots = []  # (column, row-vector, rhs)
+    for col in range(n):
+        k = next((q for q, (v, _) in enumerate(eqs) if (v >> col) & 1), None)
+        if k is None:
+            continue
+        v, c = eqs.pop(k)
+        eqs = [(w ^ v, d ^ c) if (w >> col) & 1 else (w, d) for (w, d) in eqs]
+        pivots = [(pc, w ^ v, d ^ c) if (w >> col) & 1 else (pc, w, d) for (pc, w, d) in pivots]
+        pivots.append((col, v, c))
+    if any(d for (_, d) in eqs):
+        return np.zeros(0, dtype=np.uint64)  # inconsistent (rank deficient)
+    pcols = {pc for (pc, _, _) in pivots}
+    free = [c for c in range(n) if c not in pcols]
+    # each pivot variable equals its rhs plus the free variables in its row
+    sols = []
+    for fmask in range(1 << len(free)):
+        i = 0
+        for q, c in enumerate(free):
+            if (fmask >> q) & 1:
+                i |= 1 << c
+        for (pc, v, d) in pivots:
+            bit = d ^ (bin(v & i & ~(1 << pc)).count("1") & 1)
+            i |= bit << pc
+        sols.append(i)
+    return np.array(sorted(sols), dtype=np.uint64)
 
 
 def _log2(size: int) -> int:

@@ -33,7 +33,9 @@
  * Parity status: every function here is pinned by the test-suite against
  * the Sylvester Hadamard matrix (scipy.linalg.hadamard), brute-force sums,
  * closed forms (delta, constant, Walsh function, planted peak), the
- * involution H(Hx) = 2^n x and Parseval's identity.  None is unpinned.
+ * involution H(Hx) = 2^n x and Parseval's identity; the section 5.1 fold
+ * against Hadamard matrices on the subspace, block sums, permutations and the
+ * noise-free planted peak.  None is unpinned.
  *
  * ORACLE_MUTANT=<k> plants one deliberate mistake (used only by the test that
  * proves the pins catch plausible errors); the default build plants none.
@@ -409,4 +411,51 @@ void norms_f64(const float *x, const float *y, const double *r,
         }
         sx[t] = a; sy[t] = b; se[t] = c;
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 5.1: linear space reduction of the signal                  */
+/* ------------------------------------------------------------------ */
+
+/* A : GF(2)^n -> GF(2)^m given by its m rows: bit t of A i is <rows[t], i>. */
+static uint64_t map_apply(const uint64_t *rows, int m, uint64_t i)
+{
+    uint64_t j = 0;
+    for (int t = 0; t < m; t++)
+#if ORACLE_MUTANT == 12
+        j |= (uint64_t)inner(rows[t], i) << (m - 1 - t); /* planted: rows in reverse order */
+#else
+        j |= (uint64_t)inner(rows[t], i) << t;
+#endif
+    return j;
+}
+
+/* The reduced signal u_j = sum of x_i over every i with A i = j, for all
+ * j in [0, 2^m) (wrap-around sums).  Its 2^m-point transform at k' is the
+ * 2^n-point transform of x at A^T k', the XOR of rows[t] over the set bits
+ * t of k' (subspace_index below). */
+void fold_u64(const uint64_t *x, int n, const uint64_t *rows, int m, uint64_t *u)
+{
+    memset(u, 0, sizeof(uint64_t) << m);
+    for (uint64_t i = 0; i < (1ULL << n); i++) u[map_apply(rows, m, i)] += x[i];
+}
+
+void fold_u32(const uint32_t *x, int n, const uint64_t *rows, int m, uint32_t *u)
+{
+    memset(u, 0, sizeof(uint32_t) << m);
+    for (uint64_t i = 0; i < (1ULL << n); i++) u[map_apply(rows, m, i)] += x[i];
+}
+
+/* A^T k': the index in GF(2)^n of the coefficient that entry k' of the
+ * reduced transform holds. */
+uint64_t subspace_index(const uint64_t *rows, int m, uint64_t kp)
+{
+    uint64_t k = 0;
+    for (int t = 0; t < m; t++)
+#if ORACLE_MUTANT == 13
+        if ((kp >> t) & 1) k |= rows[t]; /* planted: OR instead of XOR */
+#else
+        if ((kp >> t) & 1) k ^= rows[t];
+#endif
+    return k;
 }

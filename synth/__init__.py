@@ -137,6 +137,42 @@ def planted_ref(n: int, seed: int, p: float, dtype=np.int32, start: int = 0,
     return out, s, errors
 
 
+def planted_params(n: int, seed: int, p: float):
+    """(s, state, thr) of the planted signal: the mask, the state of the noise
+    stream and the Bernoulli threshold, which together define x_i for any i
+    (as an on-the-fly signal source regenerates it)."""
+    return planted_mask(n, seed), stream_state(seed, 2), bernoulli_threshold(p)
+
+
+def planted_at(n: int, seed: int, p: float, idx) -> np.ndarray:
+    """The planted signal (int64) at arbitrary indices `idx`; numpy definition."""
+    s, st, thr = planted_params(n, seed, p)
+    i = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    with np.errstate(over="ignore"):
+        h = _mix(np.uint64(st) + (i + np.uint64(1)) * GOLDEN)
+    e = (h >> np.uint64(32)) < np.uint64(thr)
+    par = (np.bitwise_count(i & np.uint64(s)) & np.uint8(1)).astype(bool)
+    return np.where(par ^ e, -1, 1).astype(np.int64)
+
+
+def subspace_rows(n: int, m: int, seed: int) -> np.ndarray:
+    """m random n-bit rows (uint64, numpy PCG64) for a linear space reduction
+    GF(2)^n -> GF(2)^m; redrawn until they are linearly independent."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    while True:
+        rows = rng.integers(0, 1 << n, size=m, dtype=np.uint64) if n < 64 else \
+            rng.integers(0, np.iinfo(np.uint64).max, size=m, dtype=np.uint64, endpoint=True)
+        basis = []
+        for r in (int(v) for v in rows):
+            for b in basis:
+                r = min(r, r ^ b)
+            if r:
+                basis.append(r)
+                basis.sort(reverse=True)
+        if len(basis) == m:
+            return rows
+
+
 def signs(count: int, seed: int, dtype=np.int32, start: int = 0) -> np.ndarray:
     """Uniform random signs x_i in {+1, -1} (stream 0), indices start..start+count-1."""
     out = np.empty(count, dtype=dtype)

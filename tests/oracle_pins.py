@@ -26,6 +26,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
+import oracle
 import synth
 
 
@@ -233,4 +234,134 @@ def pin_norms(O):
         assert np.isclose(se[t], np.dot(yd - r[sl], yd - r[sl]), rtol=1e-14)
 
 
-ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
+# ---- section 5.1: linear space reduction ------------------------------------
+
+def _map_numpy(rows, n):
+    """A i for every i in [0, 2^n), by brute force (bit t = parity(rows[t] & i))."""
+    i = np.arange(1 << n, dtype=np.uint64)
+    j = np.zeros(1 << n, dtype=np.uint64)
+    for t, r in enumerate(rows):
+        j |= (np.bitwise_count(i & np.uint64(int(r))) & np.uint8(1)).astype(np.uint64) << np.uint64(t)
+    return j
+
+
+def pin_fold_vs_sylvester(O):
+    # The 2^m-point transform of the reduced signal u equals the full
+    # transform on the subspace {A^T k'}: both sides by Hadamard matrices.
+    for (n, m, seed) in ((6, 3, 1), (8, 5, 2), (9, 9, 3), (7, 1, 4), (10, 6, 5)):
+        rows = synth.subspace_rows(n, m, seed)
+        x = synth.ints(1 << n, 40 + seed, -50, 50)
+        W = scipy.linalg.hadamard(1 << n, dtype=np.int64) @ x
+        u = O.fold(x, rows, m)
+        Wu = scipy.linalg.hadamard(1 << m, dtype=np.int64) @ u
+        ks = O.subspace_indices(rows, range(1 << m)).astype(np.int64)
+        assert np.array_equal(Wu, W[ks]), (n, m)
+        # the subspace has 2^m distinct members
+        assert len(set(ks.tolist())) == 1 << m
+        # int32 folds wrap like the int64 ones
+        u32 = O.fold(x.astype(np.int32), rows, m)
+        assert np.array_equal(u32, u.astype(np.int32))
+
+
+def pin_fold_special_maps(O):
+    # A = [I_m | 0] sums the 2^(n-m) blocks of 2^m consecutive entries;
+    # an invertible A (m = n) permutes x; every fold preserves the total
+    # (W(0) = sum x_i); the preimage of each j has 2^(n-m) members.
+    n, m = 9, 4
+    x = synth.ints(1 << n, 77, -1000, 1000)
+    u = O.fold(x, [1 << t for t in range(m)], m)
+    assert np.array_equal(u, x.reshape(-1, 1 << m).sum(axis=0))
+    rows = synth.subspace_rows(n, n, 8)
+    up = O.fold(x, rows, n)
+    assert np.array_equal(np.sort(up), np.sort(x))
+    j = _map_numpy(rows, n)
+    assert np.array_equal(up[j.astype(np.int64)], x)
+    rows = synth.subspace_rows(n, m, 9)
+    u = O.fold(x, rows, m)
+    assert int(u.sum()) == int(x.sum())
+    jm = _map_numpy(rows, n)
+    assert np.array_equal(np.bincount(jm.astype(np.int64), minlength=1 << m),
+                          np.full(1 << m, 1 << (n - m)))
+
+
+def pin_fold_planted_peak(O):
+    # Noise-free planted signal (p = 0) is the Walsh function chi_s: the
+    # reduced transform is 2^n at the k' with A^T k' = s when s lies in the
+    # subspace (rank test), and zero everywhere else.
+    n, m = 12, 5
+    x, s, err = synth.planted(n, 11, 0.0, np.int64)
+    assert err == 0
+    found = 0
+    for seed in range(40):
+        rows = synth.subspace_rows(n, m, 100 + seed)
+        if seed == 0:  # force one subspace through s
+            rows = np.array([s] + [int(v) for v in rows[1:]], dtype=np.uint64)
+            if oracle.gf2_rank(rows) < m:
+                continue
+        Wu = O.wht_fig1(O.fold(x, rows, m))
+        inside = oracle.gf2_rank(list(rows) + [s]) == m
+        nz = np.flatnonzero(Wu)
+        if inside:
+            found += 1
+            assert nz.size == 1 and Wu[nz[0]] == 1 << n
+            assert O.subspace_index(rows, int(nz[0])) == s
+        else:
+            assert nz.size == 0
+    assert found >= 1
+
+
+def pin_canonical_rows_and_preimage(O):
+    # The reduced echelon basis spans the same space (brute-force spans) and
+    # has unit pivot columns; fold_preimage agrees with a brute-force scan.
+    for (n, m, seed) in ((8, 4, 1), (7, 7, 2), (9, 3, 3), (6, 1, 4)):
+        rows = synth.subspace_rows(n, m, 200 + seed)
+        can = oracle.gf2_canonical_rows(rows, n)
+        assert can is not None and len(can) == m
+
+        def span(rs):
+            out = {0}
+            for r in rs:
+                out |= {v ^ int(r) for v in out}
+            return out
+        assert span(rows) == span(can)
+        piv = [v & -v for v in can]
+        assert piv == sorted(piv) and len(set(piv)) == m
+        for t, v in enumerate(can):
+            for q, p in enumerate(piv):
+                assert bool(v & p) == (q == t)
+        jm = _map_numpy(rows, n)
+        for j in (0, 1, (1 << m) - 1, (5 * seed) % (1 << m)):
+            want = np.flatnonzero(jm == j).astype(np.uint64)
+            assert np.array_equal(oracle.fold_preimage(rows, n, j), want)
+    dep = [3, 5, 6]  # 3 ^ 5 = 6
+    assert oracle.gf2_canonical_rows(dep, 4) is None and oracle.gf2_rank(dep) == 2
+
+
+def pin_subspace_coverage_example():
+    # Section 5.1's worked example: each reduction keeps 1/32 of the
+    # coefficients and 64 independent reductions cover about 87% of them.
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "subspace_coverage.txt")
+    kv = dict(l.split()[:2] for l in open(path) if l.strip() and not l.startswith("#"))
+    from fractions import Fraction
+    frac = float(Fraction(kv["fraction_per_reduction"]))
+    R, want = int(kv["reductions"]), float(kv["covered"])
+    assert round(1 - (1 - frac) ** R, 2) == want
+
+
+def pin_subspace_coverage(O):
+    # The same example scaled down to n = 10, m = 5 (fraction 1/32): the
+    # share of the 2^n - 1 nonzero coefficients that 64 random reductions
+    # reach is close to 1 - (1 - (2^m - 1)/(2^n - 1))^64.
+    pin_subspace_coverage_example()
+    n, m, R = 10, 5, 64
+    seen = np.zeros(1 << n, dtype=bool)
+    for r in range(R):
+        rows = synth.subspace_rows(n, m, 1000 + r)
+        seen[O.subspace_indices(rows, range(1 << m)).astype(np.int64)] = True
+    got = np.count_nonzero(seen[1:]) / ((1 << n) - 1)
+    p = ((1 << m) - 1) / ((1 << n) - 1)
+    assert abs(got - (1 - (1 - p) ** R)) < 0.03, got
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and k != "pin_subspace_coverage_example"]

@@ -22,8 +22,9 @@ def test_pin(O, pin):
 # 5 definition sign flipped, 6 OR instead of AND in <i,j>, 7 hit index off by
 # one, 8 ">=" instead of ">", 9 sign of the coefficient ignored in |y|,
 # 10 scale 2^-n instead of 2^-n/2, 11 Fig. 2 workload starts that ignore the
-# gap at bit k.
-MUTANTS = list(range(1, 12))
+# gap at bit k, 12 rows of the reduction map applied in reverse order, 13 OR
+# instead of XOR when mapping a reduced index back to the full space.
+MUTANTS = list(range(1, 14))
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
