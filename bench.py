@@ -200,6 +200,7 @@ def main():
     if not args.no_extras:
         out["batched"] = bench_batched(F, torch, np, synth)
         out["autograd"] = bench_autograd(F, torch, np, synth)
+        out["subspace"] = bench_subspace(F, torch, np, synth)
 
     if not args.no_cpu:
         import oracle
@@ -345,6 +346,68 @@ def bench_autograd(F, torch, np, synth):
            "GBs_per_call": round(2 * 2 * B * (1 << n) * 4 / ms_call / 1e6, 1),
            "ms_forward_loss_backward": round(ms_step, 4), "schedule": F.get_schedule("float32", n)}
     del x, w, buf
+    torch.cuda.empty_cache()
+    return res
+
+
+# VALU instructions per generated entry in the inner loop of the on-the-fly
+# reduction kernel (798 per 32 entries in its gfx950 listing), and the VALU
+# issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+FOLD_GEN_VALU_PER_ENTRY = 798 / 32
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def bench_subspace(F, torch, np, synth):
+    """Section 5.1 linear space reduction: a stored int32 signal of 2^30 entries
+    reduced to 2^24 (bound by HBM), and the planted signal of 2^40 entries
+    (seed 6, p = 0.45) generated on the fly and reduced to 2^30 (bound by
+    VALU), followed by the 2^30-point int64 transform with the threshold
+    6 * 2^20 and the hits mapped back to 40-bit indices."""
+    res = {}
+    n, m = 30, 24
+    x = torch.from_numpy(synth.signs(1 << n, 2)).cuda()
+    rows = synth.subspace_rows(n, m, 7)
+    u = torch.empty(1 << m, dtype=torch.int32, device="cuda")
+    F.fold_(x, m, rows, out=u)
+    torch.cuda.synchronize()
+    ms = _time_replays(torch, lambda: F.fold_(x, m, rows, out=u), 10)
+    algo = 4 * ((1 << n) + (1 << m))
+    res["stored"] = {"n": n, "m": m, "dtype": "int32", "ms": round(ms, 4), "GBs": round(algo / ms / 1e6, 1),
+                     "frac_of_8TBs": round(algo / ms / 1e6 / 8000.0, 4), "algorithmic_bytes": algo}
+    del x, u
+    torch.cuda.empty_cache()
+
+    n, m, p, seed = 40, 30, 0.45, 6
+    mask, state, thr = synth.planted_params(n, seed, p)
+    rows = synth.subspace_rows(n, m, 400)
+    rows[0] = np.uint64(mask)  # a reduction whose subspace holds the planted peak
+    u = torch.empty(1 << m, dtype=torch.int64, device="cuda")
+    F.fold_planted(n, m, rows, mask, state, thr, out=u)
+    torch.cuda.synchronize()
+    ms_fold = _time_replays(torch, lambda: F.fold_planted(n, m, rows, mask, state, thr, out=u), 3)
+    _, basis = F.fold_planted(n, m, rows, mask, state, thr, out=u)
+    T = int(np.ceil(6 * 2 ** (n / 2)))
+    bufs = F.hit_buffers(u, 1 << 12)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    F.fwht_int_(u, threshold=T, sync=False, hits=bufs)
+    F.subspace_hits_(bufs, basis)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_tr = e0.elapsed_time(e1)
+    cnt = int(bufs[2].cpu().item())
+    idx = bufs[0][:min(cnt, 1 << 12)].cpu().numpy()
+    rate = (1 << n) / ms_fold / 1e9  # T entries / s
+    peak = VALU_LANE_OPS_PER_S / FOLD_GEN_VALU_PER_ENTRY / 1e12
+    res["generated"] = {
+        "n": n, "m": m, "dtype": "int64", "ms_fold": round(ms_fold, 2), "Tentries_per_s": round(rate, 4),
+        "roofline": {"bound": "alu", "achieved": round(rate, 4), "peak": round(peak, 4),
+                     "unit": "T entries/s", "frac": round(rate / peak, 4),
+                     "valu_per_entry": round(FOLD_GEN_VALU_PER_ENTRY, 3)},
+        "ms_transform_threshold_remap": round(ms_tr, 3), "hits": cnt,
+        "planted_mask_recovered": bool(int(mask) in set(int(v) for v in idx)),
+        "coefficients_obtained": 1 << m, "share_of_spectrum": 2.0 ** (m - n)}
+    del u, bufs
     torch.cuda.empty_cache()
     return res
 

@@ -159,6 +159,46 @@ int fwht_get_schedule(int dtype, int n, char *buf, int len);
 int fwht_trace_enable(int on);
 int fwht_trace_read(float *ms, int cap, int *count, char *names, int names_len);
 
+/* ---- Linear space reduction (section 5.1, WHT with an on-the-fly signal
+ * source) ------------------------------------------------------------------
+ * A rank-m linear map A : GF(2)^n -> GF(2)^m, given by its m rows (HOST
+ * uint64_t[m], bits below n; bit t of A i is the parity of rows[t] & i),
+ * reduces a signal x of 2^n entries to u_j = sum of x_i over the 2^(n-m)
+ * indices i with A i = j.  The 2^m-point transform of u (fwht_int on u) then
+ * holds at k' the 2^n-point transform of x at A^T k'.  Only the row space of
+ * A decides which coefficients these are, so the library reduces by the
+ * unique reduced echelon basis of that space with pivots at the lowest bits
+ * (row t's lowest set bit p_t, p_0 < p_1 < ..., bit p_t clear in every other
+ * row) and writes it to basis (HOST uint64_t[m], written on success): entry
+ * k' of the reduced transform holds the coefficient at the XOR of basis[t]
+ * over the set bits t of k' (fwht_subspace_hits maps hit indices so).
+ * u: device, 2^m entries of dtype (FWHT_I32 or FWHT_I64), 16-byte aligned,
+ * overwritten; sums wrap modulo 2^32 / 2^64.  0 <= m <= min(n, 36).
+ * FWHT_E_INVAL for linearly dependent rows, row bits at or above n, NULL or
+ * misaligned pointers; FWHT_E_RANGE for n or m out of range.  Asynchronous
+ * on `stream`; the library allocates nothing. */
+
+/* Stored signal: x is device memory holding 2^n entries of dtype (16-byte
+ * aligned), n <= 40.  Bound by HBM: 2^n entries read, 2^m written. */
+int fwht_fold(const void *x, int dtype, int n, int m, const uint64_t *rows, void *u, uint64_t *basis,
+              void *stream);
+
+/* Generated signal: the planted signal x_i = (-1)^(<mask, i> xor e_i) with
+ * noise bit e_i = [(h_i >> 32) < thr], h_i = SplitMix64 output i of the
+ * stream with state `state` (Steele, Lea and Flood, OOPSLA 2014), computed on
+ * the fly inside the reduction: x never exists in memory.  n <= 48, mask
+ * below 2^n.  Bound by integer ALU (one SplitMix64 output per entry). */
+int fwht_fold_planted(int dtype, int n, int m, const uint64_t *rows, uint64_t mask, uint64_t state,
+                      uint64_t thr, void *u, uint64_t *basis, void *stream);
+
+/* Rewrites the first min(*count, cap) hit indices k' of a threshold on the
+ * reduced transform (idx, count: device, as filled by fwht_int's fused
+ * threshold) to the full-space indices A^T k' = XOR of basis[t] over the set
+ * bits t of k' (basis: HOST uint64_t[m] from fwht_fold / fwht_fold_planted).
+ * Asynchronous on `stream`. */
+int fwht_subspace_hits(uint64_t *idx, uint64_t cap, const uint64_t *count, int m, const uint64_t *basis,
+                       void *stream);
+
 /* Utility for measurement: plain device-to-device copy of `bytes` bytes
  * (16-byte aligned pointers, bytes a multiple of 16), the reference kernel
  * whose traffic calibrates the HBM counters.  Asynchronous. */

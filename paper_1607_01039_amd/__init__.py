@@ -30,7 +30,7 @@ PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
 
 __all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
            "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
-           "FWHTError", "PRECISIONS"]
+           "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "FWHTError", "PRECISIONS"]
 
 
 def _torch():
@@ -133,6 +133,84 @@ def fwht_int_(t, threshold=None, cap: int = 1 << 16, sync: bool = True, hits=Non
         return bufs
     if t.is_cuda:
         torch.cuda.current_stream().synchronize()
+    return _collect(*bufs, cap)
+
+
+# ---- section 5.1: linear space reduction -------------------------------------
+
+def _rows_array(rows, m):
+    r = np.ascontiguousarray(np.asarray(rows, dtype=np.uint64).reshape(-1))
+    if r.size != m:
+        raise ValueError(f"expected {m} rows, got {r.size}")
+    return r
+
+
+def fold_(x, m: int, rows, out=None):
+    """Reduce a stored signal (1-D int32/int64 CUDA tensor of 2^n entries) by the
+    linear map A : GF(2)^n -> GF(2)^m with the given rows (bit t of A i is the
+    parity of rows[t] & i): u_j = sum of x_i over A i = j.  Returns (u, basis):
+    u (2^m entries, x's dtype) is the reduction by the canonical basis of the
+    row space, and entry k' of u's transform is the coefficient of x at the
+    XOR of basis[t] over the set bits t of k'."""
+    torch = _torch()
+    if x.dim() != 1 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("fold_ needs a contiguous 1-D CUDA tensor")
+    dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64}.get(x.dtype)
+    if dt is None:
+        raise TypeError("fold_ needs int32 or int64")
+    n = _log2(x.numel())
+    r = _rows_array(rows, m)
+    if out is None:
+        out = torch.empty(1 << m, dtype=x.dtype, device=x.device)
+    if out.numel() != 1 << m or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of 2^m entries of x's dtype")
+    basis = np.zeros(max(m, 1), dtype=np.uint64)
+    _lib.check(_lib.lib().fwht_fold(C.c_void_p(x.data_ptr()), dt, n, m, r.ctypes.data_as(C.c_void_p),
+                                    C.c_void_p(out.data_ptr()), basis.ctypes.data_as(C.c_void_p),
+                                    _stream_ptr(x)))
+    return out, basis[:m]
+
+
+def fold_planted(n: int, m: int, rows, mask: int, state: int, thr: int, dtype=None, out=None,
+                 device="cuda"):
+    """Reduce the planted signal x_i = (-1)^(<mask, i> xor [(h_i >> 32) < thr])
+    (h_i: SplitMix64 output i of the stream with `state`), generated on the fly
+    inside the reduction, to 2^m entries.  Returns (u, basis) as ``fold_``."""
+    torch = _torch()
+    dtype = torch.int64 if dtype is None else dtype
+    dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64}.get(dtype)
+    if dt is None:
+        raise TypeError("fold_planted needs int32 or int64")
+    r = _rows_array(rows, m)
+    if out is None:
+        out = torch.empty(1 << m, dtype=dtype, device=device)
+    if out.numel() != 1 << m or out.dtype != dtype or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous CUDA tensor of 2^m entries of `dtype`")
+    basis = np.zeros(max(m, 1), dtype=np.uint64)
+    _lib.check(_lib.lib().fwht_fold_planted(dt, n, m, r.ctypes.data_as(C.c_void_p), int(mask), int(state),
+                                            int(thr), C.c_void_p(out.data_ptr()),
+                                            basis.ctypes.data_as(C.c_void_p), _stream_ptr(out)))
+    return out, basis[:m]
+
+
+def subspace_hits_(bufs, basis) -> None:
+    """Map the hit indices k' of a threshold on a reduced transform, in the
+    device buffers (idx, val, count) from ``fwht_int_(..., sync=False)``, to
+    the full-space indices (XOR of basis[t] over the set bits t of k')."""
+    idx, _, cnt = bufs
+    b = np.ascontiguousarray(np.asarray(basis, dtype=np.uint64))
+    _lib.check(_lib.lib().fwht_subspace_hits(C.c_void_p(idx.data_ptr()), int(idx.numel()),
+                                             C.c_void_p(cnt.data_ptr()), int(b.size),
+                                             b.ctypes.data_as(C.c_void_p), _stream_ptr(idx)))
+
+
+def subspace_transform(u, basis, threshold, cap: int = 1 << 16, hits=None) -> Hits:
+    """Transform a reduced signal u in place (2^m-point WHT) and return the
+    coefficients above ``threshold`` with their full-space indices."""
+    bufs = fwht_int_(u, threshold=threshold, cap=cap, sync=False, hits=hits)
+    cap = int(bufs[0].numel())
+    subspace_hits_(bufs, basis)
+    _torch().cuda.current_stream().synchronize()
     return _collect(*bufs, cap)
 
 

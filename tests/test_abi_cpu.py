@@ -104,3 +104,32 @@ def test_product_does_not_import_oracle():
     code = ("import sys, paper_1607_01039_amd as p; p._lib.lib();"
             "assert 'oracle' not in sys.modules, 'product imported the oracle'")
     subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
+
+
+def test_fold_validation(L):
+    from paper_1607_01039_amd import _lib
+    import numpy as np
+    keep, p = _buf()
+    rows = np.array([0b0011, 0b0101, 0b1000], dtype=np.uint64)
+    basis = np.zeros(4, dtype=np.uint64)
+    rp, bp = rows.ctypes.data_as(C.c_void_p), basis.ctypes.data_as(C.c_void_p)
+    x, u = C.c_void_p(p), C.c_void_p(p)
+    assert L.fwht_fold(x, 7, 4, 3, rp, u, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_fold(x, 0, 41, 3, rp, u, bp, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_fold(x, 0, 4, 5, rp, u, bp, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_fold(None, 0, 4, 3, rp, u, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_fold(C.c_void_p(p + 4), 0, 4, 3, rp, u, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_fold(x, 0, 4, 3, None, u, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_fold(x, 0, 3, 3, rp, u, bp, None) == _lib.FWHT_E_INVAL  # row bit 3 >= n
+    assert b"at or above" in L.fwht_last_error()
+    dep = np.array([0b0011, 0b0101, 0b0110], dtype=np.uint64)  # third = first ^ second
+    assert L.fwht_fold(x, 1, 4, 3, dep.ctypes.data_as(C.c_void_p), u, bp, None) == _lib.FWHT_E_INVAL
+    assert b"dependent" in L.fwht_last_error()
+    assert not basis.any()  # nothing written on failure
+    assert L.fwht_fold_planted(0, 49, 3, rp, 0, 1, 2, u, bp, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_fold_planted(0, 4, 3, rp, 1 << 4, 1, 2, u, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_fold_planted(0, 4, 3, rp, 0, 1, 2, None, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_subspace_hits(x, 4, None, 3, bp, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_subspace_hits(x, 4, x, 37, bp, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_subspace_hits(x, 4, x, 3, None, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_subspace_hits(x, 0, x, 3, bp, None) == _lib.FWHT_OK  # nothing to map
