@@ -13,7 +13,8 @@ unnormalised) and the algorithms of Fig. 1 (serial in-place butterflies),
 Fig. 2 (fork-join parallel decomposition) and Fig. 3 (external block scheme).
 Section 5.1's linear space reduction (the fold u_j = sum_{A i = j} x_i and
 the index map k' -> A^T k') is here too, with a plain GF(2) elimination
-(canonical basis, preimage of one reduced index) in Python.
+(canonical basis, preimage of one reduced index) in Python, and the prime-factor
+counts Omega(i) of the workload announced in section 4.3.
 Integer results are wrap-around (mod 2^32 for int32 data, mod 2^64 for int64);
 floating point is IEEE double on the exactly up-cast input.
 """
@@ -90,6 +91,10 @@ class Oracle:
         L.fold_u32.argtypes = [_u32p, C.c_int, _u64p, C.c_int, _u32p]
         L.subspace_index.argtypes = [_u64p, C.c_int, C.c_uint64]
         L.subspace_index.restype = C.c_uint64
+        L.prime_omega.argtypes = [C.c_uint64, _i32p]
+        L.prime_omega.restype = C.c_int
+        L.prime_omega_at.argtypes = [C.c_uint64]
+        L.prime_omega_at.restype = C.c_int32
 
     # ---- Eq. 2 written out ------------------------------------------------
     def wht_def(self, x: np.ndarray) -> np.ndarray:
@@ -257,6 +262,19 @@ class Oracle:
 
     def subspace_indices(self, rows, kps) -> np.ndarray:
         return np.array([self.subspace_index(rows, k) for k in kps], dtype=np.uint64)
+
+    # ---- prime-factor counts (the workload announced in section 4.3) --------
+    def prime_omega(self, count: int) -> np.ndarray:
+        """Omega(i) (prime factors with multiplicity; Omega(0) = Omega(1) = 0)
+        for i in [0, count), int32."""
+        out = np.empty(max(count, 1), dtype=np.int32)
+        if self._L.prime_omega(count, out) != 0:
+            raise MemoryError("prime_omega")
+        return out[:count]
+
+    def prime_omega_at(self, ks) -> np.ndarray:
+        """Omega(k) of single numbers by trial division."""
+        return np.array([self._L.prime_omega_at(int(k)) for k in ks], dtype=np.int64)
 
 
 # ---- GF(2) linear algebra for section 5.1 (plain Gaussian elimination) ------

@@ -35,7 +35,9 @@
  * closed forms (delta, constant, Walsh function, planted peak), the
  * involution H(Hx) = 2^n x and Parseval's identity; the section 5.1 fold
  * against Hadamard matrices on the subspace, block sums, permutations and the
- * noise-free planted peak.  None is unpinned.
+ * noise-free planted peak; the prime-factor counts against their definition
+ * on small numbers, primes and prime powers from an independent sieve,
+ * complete additivity and Legendre's formula.  None is unpinned.
  *
  * ORACLE_MUTANT=<k> plants one deliberate mistake (used only by the test that
  * proves the pins catch plausible errors); the default build plants none.
@@ -458,4 +460,49 @@ uint64_t subspace_index(const uint64_t *rows, int m, uint64_t kp)
         if ((kp >> t) & 1) k ^= rows[t];
 #endif
     return k;
+}
+
+/* ------------------------------------------------------------------ */
+/* Prime-factor counts (the workload announced in section 4.3)        */
+/* ------------------------------------------------------------------ */
+
+/* out[i] = Omega(i), the number of prime factors of i counted with
+ * multiplicity (Omega(0) = Omega(1) = 0), for i in [0, count): a
+ * smallest-prime-factor sieve, then repeated division. */
+int prime_omega(uint64_t count, int32_t *out)
+{
+    uint32_t *spf = calloc(count > 2 ? count : 2, sizeof(uint32_t));
+    if (!spf) return -1;
+    for (uint64_t i = 2; i < count; i++) {
+        if (spf[i]) continue;
+        for (uint64_t j = i; j < count; j += i)
+            if (!spf[j]) spf[j] = (uint32_t)i;
+    }
+    for (uint64_t i = 0; i < count; i++) {
+        int32_t c = 0;
+        for (uint64_t v = i; v > 1; v /= spf[v]) c++;
+#if ORACLE_MUTANT == 14
+        if (i > 1 && spf[i] == i) c = 1; else if (i > 3 && i % 4 == 0) c--; /* planted: a square of 2 counted once */
+#endif
+        out[i] = c;
+    }
+    free(spf);
+    return 0;
+}
+
+/* Omega(i) of one number by trial division. */
+int32_t prime_omega_at(uint64_t i)
+{
+    if (i < 2) return 0;
+    int32_t c = 0;
+    for (uint64_t p = 2; p * p <= i; p++)
+        while (i % p == 0) {
+            i /= p;
+            c++;
+        }
+#if ORACLE_MUTANT == 15
+    return c; /* planted: the last prime factor above the square root is dropped */
+#else
+    return c + (i > 1);
+#endif
 }

@@ -364,4 +364,57 @@ def pin_subspace_coverage(O):
     assert abs(got - (1 - (1 - p) ** R)) < 0.03, got
 
 
+# ---- prime-factor counts (section 4.3's announced workload) ----------------
+
+def _primes_upto(n):
+    """Sieve of Eratosthenes (boolean numpy), independent of the oracle."""
+    ok = np.ones(n + 1, dtype=bool)
+    ok[:2] = False
+    for p in range(2, int(n ** 0.5) + 1):
+        if ok[p]:
+            ok[p * p::p] = False
+    return np.flatnonzero(ok)
+
+
+def pin_omega_definition(O):
+    # Omega of 0 .. 20 written out from the factorisations (0 and 1 have none).
+    want = [0, 0, 1, 1, 2, 1, 2, 1, 3, 2, 2, 1, 3, 1, 2, 2, 4, 1, 3, 1, 3]
+    assert O.prime_omega(21).tolist() == want
+    assert O.prime_omega_at(range(21)).tolist() == want
+    om = O.prime_omega(1 << 16)
+    ps = _primes_upto((1 << 16) - 1)
+    assert np.all(om[ps] == 1)
+    for p in (2, 3, 5, 7, 251):
+        k = 1
+        while p ** k < (1 << 16):
+            assert om[p ** k] == k
+            k += 1
+    assert om.sum() == int(O.prime_omega_at(range(1 << 16)).sum())
+
+
+def pin_omega_additive_and_legendre(O):
+    # Omega is completely additive, Omega(ab) = Omega(a) + Omega(b), and by
+    # Legendre's formula sum_{i <= N} Omega(i) = sum over prime powers p^k <= N
+    # of floor(N / p^k).
+    n = 20
+    N = (1 << n) - 1
+    om = O.prime_omega(1 << n)
+    rng = np.random.default_rng(3)
+    a = rng.integers(1, 1 << 10, size=2000)
+    b = rng.integers(1, 1 << 10, size=2000)
+    assert np.array_equal(om[a * b], om[a] + om[b])
+    tot = 0
+    for p in _primes_upto(N).tolist():
+        q = p
+        while q <= N:
+            tot += N // q
+            q *= p
+    assert int(om.astype(np.int64).sum()) == tot
+    # trial division on large numbers: products of known primes
+    ps = _primes_upto(40000)
+    for (x, k) in ((1 << 30, 30), (3 ** 18, 18), (int(ps[-1]) * int(ps[-2]), 2),
+                   (int(ps[-1]) * int(ps[100]) * 4, 4), (int(ps[-1]) ** 2, 2), (int(ps[-1]), 1)):
+        assert O.prime_omega_at([x])[0] == k, x
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and k != "pin_subspace_coverage_example"]

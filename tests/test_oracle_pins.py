@@ -23,8 +23,10 @@ def test_pin(O, pin):
 # one, 8 ">=" instead of ">", 9 sign of the coefficient ignored in |y|,
 # 10 scale 2^-n instead of 2^-n/2, 11 Fig. 2 workload starts that ignore the
 # gap at bit k, 12 rows of the reduction map applied in reverse order, 13 OR
-# instead of XOR when mapping a reduced index back to the full space.
-MUTANTS = list(range(1, 14))
+# instead of XOR when mapping a reduced index back to the full space, 14 a
+# square factor 2^2 counted once in the prime-factor counts, 15 the last prime
+# factor above the square root dropped by trial division.
+MUTANTS = list(range(1, 16))
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
