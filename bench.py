@@ -201,6 +201,7 @@ def main():
         out["batched"] = bench_batched(F, torch, np, synth)
         out["autograd"] = bench_autograd(F, torch, np, synth)
         out["subspace"] = bench_subspace(F, torch, np, synth)
+        out["prime_omega"] = bench_prime_omega(F, torch, np)
 
     if not args.no_cpu:
         import oracle
@@ -408,6 +409,30 @@ def bench_subspace(F, torch, np, synth):
         "planted_mask_recovered": bool(int(mask) in set(int(v) for v in idx)),
         "coefficients_obtained": 1 << m, "share_of_spectrum": 2.0 ** (m - n)}
     del u, bufs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_prime_omega(F, torch, np):
+    """The prime-factor-count signal of section 4.3 at n = 30: the segmented
+    sieve writing Omega(i) as int64 (2^30 x 8 B), then its in-HBM int64
+    transform with the coefficients above 2^30 / 8 extracted."""
+    n = 30
+    x = F.prime_omega(n)
+    torch.cuda.synchronize()
+    ms_sieve = _time_replays(torch, lambda: F.prime_omega(n, out=x), 5)
+    total = int(x.sum().item())
+    bufs = F.hit_buffers(x, 1 << 12)
+    ms_tr = _time_replays(torch, lambda: F.fwht_int_(x, threshold=(1 << n) // 8, sync=False, hits=bufs), 1,
+                          flush=lambda: F.prime_omega(n, out=x))
+    cnt = int(bufs[2].cpu().item())
+    idx = bufs[0][:min(cnt, 1 << 12)].cpu().numpy()
+    val = bufs[1][:min(cnt, 1 << 12)].cpu().numpy()
+    top = sorted(zip(idx.tolist(), val.tolist()), key=lambda kv: -abs(kv[1]))[:4]
+    res = {"n": n, "dtype": "int64", "ms_sieve": round(ms_sieve, 3),
+           "GBs_written": round(8 * (1 << n) / ms_sieve / 1e6, 1), "ms_transform": round(ms_tr, 3),
+           "sum_omega": total, "hits_above_2^27": cnt, "largest": [[int(k), int(v)] for k, v in top]}
+    del x, bufs
     torch.cuda.empty_cache()
     return res
 

@@ -199,6 +199,16 @@ int fwht_fold_planted(int dtype, int n, int m, const uint64_t *rows, uint64_t ma
 int fwht_subspace_hits(uint64_t *idx, uint64_t cap, const uint64_t *count, int m, const uint64_t *basis,
                        void *stream);
 
+/* Prime-factor counts, the signal whose transform section 4.3 announces as
+ * its first practical workload: data[i] = Omega(i), the number of prime
+ * factors of i counted with multiplicity (Omega(0) = Omega(1) = 0), for i in
+ * [0, 2^n).  data: device, 2^n entries of dtype (FWHT_I32 or FWHT_I64; the
+ * transform of n >= 29 needs FWHT_I64), 16-byte aligned, overwritten.
+ * 0 <= n <= 32 (FWHT_E_RANGE above).  A segmented sieve; the call allocates
+ * and uploads a small table of prime powers (stream-ordered) and waits for
+ * that upload, then runs asynchronously on `stream`. */
+int fwht_prime_omega(void *data, int dtype, int n, void *stream);
+
 /* Utility for measurement: plain device-to-device copy of `bytes` bytes
  * (16-byte aligned pointers, bytes a multiple of 16), the reference kernel
  * whose traffic calibrates the HBM counters.  Asynchronous. */

@@ -30,7 +30,8 @@ PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
 
 __all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
            "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
-           "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "FWHTError", "PRECISIONS"]
+           "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "prime_omega",
+           "FWHTError", "PRECISIONS"]
 
 
 def _torch():
@@ -212,6 +213,23 @@ def subspace_transform(u, basis, threshold, cap: int = 1 << 16, hits=None) -> Hi
     subspace_hits_(bufs, basis)
     _torch().cuda.current_stream().synchronize()
     return _collect(*bufs, cap)
+
+
+def prime_omega(n: int, dtype=None, out=None, device="cuda"):
+    """The prime-factor-count signal Omega(i), i in [0, 2^n) (prime factors with
+    multiplicity; Omega(0) = Omega(1) = 0), computed on the GPU (int64 by
+    default: its transform exceeds int32 from n = 29)."""
+    torch = _torch()
+    dtype = torch.int64 if dtype is None else dtype
+    dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64}.get(dtype)
+    if dt is None:
+        raise TypeError("prime_omega needs int32 or int64")
+    if out is None:
+        out = torch.empty(1 << n, dtype=dtype, device=device)
+    if out.numel() != 1 << n or out.dtype != dtype or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous CUDA tensor of 2^n entries of `dtype`")
+    _lib.check(_lib.lib().fwht_prime_omega(C.c_void_p(out.data_ptr()), dt, n, _stream_ptr(out)))
+    return out
 
 
 def fwht_float_(t, normalize: bool = True, precision: str = "fp32"):

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "FWHT_OK", 1: "FWHT_E_INVAL", 2: "FWHT_E_RANGE", 3: "FWHT_E_C
 # Every symbol include/fwht.h declares.
 EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
            "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_trace_enable", "fwht_trace_read",
-           "fwht_copy", "fwht_fold", "fwht_fold_planted", "fwht_subspace_hits", "fwht_last_error",
+           "fwht_copy", "fwht_fold", "fwht_fold_planted", "fwht_subspace_hits", "fwht_prime_omega", "fwht_last_error",
            "fwht_version")
 
 
@@ -67,12 +67,13 @@ def lib() -> C.CDLL:
     L.fwht_fold.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
     L.fwht_fold_planted.argtypes = [i32, i32, i32, vp, u64, u64, u64, vp, vp, vp]
     L.fwht_subspace_hits.argtypes = [vp, u64, vp, i32, vp, vp]
+    L.fwht_prime_omega.argtypes = [vp, i32, i32, vp]
     L.fwht_last_error.restype = C.c_char_p
     L.fwht_version.restype = C.c_char_p
     for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
                  "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_copy",
                  "fwht_trace_enable", "fwht_trace_read", "fwht_fold", "fwht_fold_planted",
-                 "fwht_subspace_hits"):
+                 "fwht_subspace_hits", "fwht_prime_omega"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
