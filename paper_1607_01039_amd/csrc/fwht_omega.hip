@@ -3,21 +3,26 @@
 // the practical distribution whose transform section 4.3 announces.
 //
 // Segmented sieve in LDS.  A workgroup owns a segment of S = 2^15 consecutive
-// integers [L, L + S) with one 32-bit word each.  Every odd prime power
-// q = p^k <= N (p <= sqrt(N), N = 2^n - 1) adds (1 << 26) + round(log2(p) 2^16)
-// to the words of its multiples: the top six bits count prime factors, the
-// low 26 bits sum their base-2 logarithms in fixed point.  The factor 2 comes
-// from the trailing zeros of i.  What is left of i after the sieved factors is
-// 1 or a single prime above sqrt(N) (two such primes would exceed N); it is
-// at least 3, so it shows as a logarithm gap of more than 1 between log2(i)
-// and the sum, far above the rounding of either (below 2^-10).
+// integers [L, L + S), 16 bits each (two to a 32-bit word, 64 KiB).  Every odd
+// prime power q = p^k <= N (p <= sqrt(N), N = 2^n - 1) adds
+// (1 << 11) + round(32 log2(p)) to the entries of its multiples: bits 11..15
+// count prime factors (at most 20 odd ones below 2^32), bits 0..10 sum their
+// base-2 logarithms in units of 1/32 (below 2048 because i < 2^32), so an
+// entry never carries into its neighbour.  The factor 2 comes from the
+// trailing zeros of i.  What is left of i after the sieved factors is 1 or a
+// single prime above sqrt(N) (two such primes would exceed N); it is at least
+// 3, so it shows as a logarithm gap of at least log2(3) = 1.58 between log2(i)
+// and the sum, while the rounding of the sum stays below 20 / 64 = 0.31: a gap
+// above 0.8 adds the last factor.
 //
-// Load balance: the multiples of q in a segment are cut into chunks of at most
-// 32, and each (q, chunk) pair is an item; items are dealt round-robin to the
-// 1024 threads (at most 16 each).  Workgroups are persistent (one per CU, the
-// segment taking 128 KiB of LDS) and walk the segments with a fixed stride D,
-// so each item's residue r = L mod q is carried in a register from one segment
-// to the next as r <- (r + D mod q) mod q.
+// Load balance: the multiples of q in a segment are dealt to C = ceil(count / 32)
+// chunks (chunk c takes every C-th multiple from the c-th, so that adjacent
+// lanes hit adjacent multiples and distinct LDS banks), and each (q, chunk)
+// pair is an item; items sorted by work are dealt
+// round-robin to the 1024 threads.  Workgroups are persistent (two per CU, so
+// that the atomics of one overlap the stores of the other).  Each item finds
+// its first multiple from L mod q, with the quotient taken from L times the
+// FP64 reciprocal of q (exact or one off, then corrected).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,60 +36,80 @@ namespace fwht {
 constexpr int kOmegaSegBits = 15;
 constexpr uint32_t kOmegaSeg = 1u << kOmegaSegBits;
 constexpr int kOmegaThreads = 1024;
-constexpr int kOmegaMaxItemsPerThread = 16;
+constexpr int kOmegaBlocksPerCU = 2;
+constexpr int kOmegaMaxItems = 1 << 16;
 constexpr uint32_t kOmegaChunk = 32;  // multiples per item and segment
 constexpr int kOmegaMaxN = 32;
 
 struct OmegaItem {
     uint32_t q;   // prime power
-    uint32_t d;   // (grid stride in integers) mod q
-    uint32_t w;   // (1 << 26) + round(log2(p) * 2^16)
-    uint32_t c0;  // first multiple of this chunk, counted from the segment's first
+    uint32_t w;   // (1 << 11) + round(32 log2(p))
+    uint32_t c0;  // this chunk takes multiples c0, c0 + cs, c0 + 2 cs, ... (counted from the
+    uint32_t cs;  // segment's first): adjacent lanes hit adjacent multiples, i.e. distinct banks
+    double inv;   // 1 / q
 };
 
 template <class T>
-__global__ void __launch_bounds__(kOmegaThreads, 1)
+// two workgroups of 16 waves per CU: 8 waves per SIMD
+__global__ void __launch_bounds__(kOmegaThreads, kOmegaBlocksPerCU * kOmegaThreads / 256)
     omega_kernel(T *__restrict__ out, const OmegaItem *__restrict__ items, uint32_t nitems, uint32_t nseg,
                  uint32_t len)
 {
-    __shared__ uint32_t seg[kOmegaSeg];
+    __shared__ uint32_t seg[kOmegaSeg / 2];
     const uint32_t t = threadIdx.x;
-    uint32_t r[kOmegaMaxItemsPerThread];
-#pragma unroll
-    for (int k = 0; k < kOmegaMaxItemsPerThread; ++k) {
-        const uint32_t it = t + (uint32_t)k * kOmegaThreads;
-        r[k] = it < nitems ? (uint32_t)(((uint64_t)blockIdx.x * kOmegaSeg) % items[it].q) : 0u;
-    }
+    const uint32_t words = (len + 1) / 2;
     for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        for (uint32_t j = t; j < len; j += kOmegaThreads) seg[j] = 0;
+        const uint32_t L = sg * kOmegaSeg;  // n <= 32: every index fits in 32 bits
+        for (uint32_t j = t; j < words; j += kOmegaThreads) seg[j] = 0;
         __syncthreads();
+        // four items per round, their loads issued together
+        for (uint32_t it0 = t; it0 < nitems; it0 += 4 * kOmegaThreads) {
+            OmegaItem mm[4];
 #pragma unroll
-        for (int k = 0; k < kOmegaMaxItemsPerThread; ++k) {
-            const uint32_t it = t + (uint32_t)k * kOmegaThreads;
-            if (it < nitems) {
-                const OmegaItem m = items[it];
-                const uint64_t f = r[k] ? (uint64_t)(m.q - r[k]) : 0ull;  // first multiple of q at or after L
-                const uint64_t j0 = f + (uint64_t)m.c0 * m.q;
-                const uint64_t j1 = std::min<uint64_t>(len, j0 + (uint64_t)kOmegaChunk * m.q);
-                for (uint64_t j = j0; j < j1; j += m.q) atomicAdd(&seg[(uint32_t)j], m.w);
-                r[k] = r[k] >= m.q - m.d ? r[k] - (m.q - m.d) : r[k] + m.d;
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t it = it0 + (uint32_t)u * kOmegaThreads;
+                mm[u] = items[it < nitems ? it : it0];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (it0 + (uint32_t)u * kOmegaThreads >= nitems) break;
+                const OmegaItem &m = mm[u];
+                // L mod q: the FP64 quotient estimate is exact or one off
+                const uint32_t qe = (uint32_t)((double)L * m.inv);
+                int64_t rr = (int64_t)L - (int64_t)qe * m.q;
+                rr = rr < 0 ? rr + m.q : (rr >= (int64_t)m.q ? rr - m.q : rr);
+                const uint64_t f = rr ? (uint64_t)(m.q - rr) : 0ull;  // first multiple of q at or after L
+                const uint64_t step = (uint64_t)m.cs * m.q;
+                for (uint64_t j = f + (uint64_t)m.c0 * m.q; j < len; j += step)
+                    atomicAdd(&seg[(uint32_t)j >> 1], m.w << (((uint32_t)j & 1u) * 16u));
             }
         }
         __syncthreads();
-        const uint32_t L = sg * kOmegaSeg;  // n <= 32: every index fits in 32 bits
         T *o = out + L;
-        for (uint32_t j = t; j < len; j += kOmegaThreads) {
-            const uint32_t i = L + j;
-            const uint32_t wd = seg[j];
-            int32_t om = 0;
-            if (i > 1) {
-                const uint32_t tz = (uint32_t)__builtin_ctz(i);
-                const float logsum = (float)((wd & 0x3FFFFFFu) + (tz << 16)) * (1.0f / 65536.0f);
-                // native log2 (relative error ~2^-22): the gap is ~0 or >= log2(3)
-                const float gap = __log2f((float)i) - logsum;
-                om = (int32_t)((wd >> 26) + tz) + (gap > 1.0f ? 1 : 0);
+        for (uint32_t w = t; w < words; w += kOmegaThreads) {
+            const uint32_t two = seg[w];
+            int32_t om[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t i = L + 2 * w + h;
+                const uint32_t e = (two >> (16 * h)) & 0xFFFFu;
+                om[h] = 0;
+                if (i > 1) {
+                    const uint32_t tz = (uint32_t)__builtin_ctz(i);
+                    const float logsum = (float)((e & 2047u) + (tz << 5)) * (1.0f / 32.0f);
+                    // native log2 (relative error ~2^-22): the gap is below 0.31 or above 1.27
+                    const float gap = __log2f((float)i) - logsum;
+                    om[h] = (int32_t)((e >> 11) + tz) + (gap > 0.8f ? 1 : 0);
+                }
             }
-            o[j] = (T)om;
+            if (2 * w + 1 < len) {  // both entries: one 8- or 16-byte store
+                if constexpr (sizeof(T) == 8)
+                    *reinterpret_cast<longlong2 *>(o + 2 * w) = make_longlong2(om[0], om[1]);
+                else
+                    *reinterpret_cast<int2 *>(o + 2 * w) = make_int2(om[0], om[1]);
+            } else {
+                o[2 * w] = (T)om[0];
+            }
         }
         __syncthreads();  // the next segment clears the words read above
     }
@@ -104,8 +129,7 @@ static int omega(void *data, int dtype, int n, hipStream_t s)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    const uint32_t grid = std::min<uint32_t>(nseg, (uint32_t)std::max(cus, 1));
-    const uint64_t D = (uint64_t)grid * kOmegaSeg;  // integers between a workgroup's segments
+    const uint32_t grid = std::min<uint32_t>(nseg, (uint32_t)std::max(cus, 1) * kOmegaBlocksPerCU);
 
     // odd primes p <= sqrt(N) by a sieve of Eratosthenes
     uint64_t root = (uint64_t)std::sqrt((double)N);
@@ -116,12 +140,12 @@ static int omega(void *data, int dtype, int n, hipStream_t s)
     for (uint64_t p = 3; p <= root; p += 2) {
         if (comp[p]) continue;
         for (uint64_t j = p * p; j <= root; j += 2 * p) comp[j] = 1;
-        const uint32_t w = (1u << 26) + (uint32_t)std::lround(std::log2((double)p) * 65536.0);
+        const uint32_t w = (1u << 11) + (uint32_t)std::lround(std::log2((double)p) * 32.0);
         for (uint64_t q = p; q <= N; q *= p) {
             const uint64_t per_seg = (len + q - 1) / q;  // most multiples of q in one segment
             const uint64_t chunks = (per_seg + kOmegaChunk - 1) / kOmegaChunk;
             for (uint64_t c = 0; c < chunks; ++c)
-                items.push_back(OmegaItem{(uint32_t)q, (uint32_t)(D % q), w, (uint32_t)(c * kOmegaChunk)});
+                items.push_back(OmegaItem{(uint32_t)q, w, (uint32_t)c, (uint32_t)chunks, 1.0 / (double)q});
             if (q > N / p) break;
         }
     }
@@ -129,11 +153,11 @@ static int omega(void *data, int dtype, int n, hipStream_t s)
     // so the lanes of a wave walk loops of the same length.
     auto work = [len](const OmegaItem &m) {
         const uint64_t per_seg = ((uint64_t)len + m.q - 1) / m.q;
-        return std::min<uint64_t>(kOmegaChunk, per_seg - m.c0);
+        return (per_seg - m.c0 + m.cs - 1) / m.cs;
     };
     std::stable_sort(items.begin(), items.end(),
                      [&](const OmegaItem &a, const OmegaItem &b) { return work(a) > work(b); });
-    if (items.size() > (size_t)kOmegaThreads * kOmegaMaxItemsPerThread)
+    if (items.size() > (size_t)kOmegaMaxItems)
         return fail(FWHT_E_RANGE, "too many sieve items (%zu)", items.size());
 
     // Items in stream-ordered memory: allocated, filled, read and released in
