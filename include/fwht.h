@@ -204,9 +204,10 @@ int fwht_subspace_hits(uint64_t *idx, uint64_t cap, const uint64_t *count, int m
  * factors of i counted with multiplicity (Omega(0) = Omega(1) = 0), for i in
  * [0, 2^n).  data: device, 2^n entries of dtype (FWHT_I32 or FWHT_I64; the
  * transform of n >= 29 needs FWHT_I64), 16-byte aligned, overwritten.
- * 0 <= n <= 32 (FWHT_E_RANGE above).  A segmented sieve; the call allocates
- * and uploads a small table of prime powers (stream-ordered) and waits for
- * that upload, then runs asynchronously on `stream`. */
+ * 0 <= n <= 32 (FWHT_E_RANGE above).  A segmented sieve.  The first call for
+ * a given (device, n) builds a table of prime powers on the host and keeps it
+ * in device memory until the process ends (at most 370 KB); every call then
+ * runs asynchronously on `stream`. */
 int fwht_prime_omega(void *data, int dtype, int n, void *stream);
 
 /* Utility for measurement: plain device-to-device copy of `bytes` bytes

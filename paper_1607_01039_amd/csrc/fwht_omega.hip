@@ -27,6 +27,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "fwht_internal.hpp"
@@ -115,22 +117,25 @@ __global__ void __launch_bounds__(kOmegaThreads, kOmegaBlocksPerCU * kOmegaThrea
     }
 }
 
-static int omega(void *data, int dtype, int n, hipStream_t s)
-{
-    if (!data) return fail(FWHT_E_INVAL, "data is NULL");
-    if (((uintptr_t)data) & 15) return fail(FWHT_E_INVAL, "data must be 16-byte aligned");
-    if (dtype != FWHT_I32 && dtype != FWHT_I64) return fail(FWHT_E_INVAL, "dtype must be FWHT_I32 or FWHT_I64");
-    if (n < 0 || n > kOmegaMaxN) return fail(FWHT_E_RANGE, "prime-factor counts need 0 <= n <= %d", kOmegaMaxN);
-    const uint64_t total = 1ull << n;
-    const uint64_t N = total - 1;
-    const uint32_t len = (uint32_t)std::min<uint64_t>(total, kOmegaSeg);
-    const uint32_t nseg = (uint32_t)(total / len);
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e, "device query");
-    const uint32_t grid = std::min<uint32_t>(nseg, (uint32_t)std::max(cus, 1) * kOmegaBlocksPerCU);
+// The item table of one (device, n): built on the host at the first call and
+// kept in device memory until the process ends (read-only afterwards, so
+// concurrent calls share it); at most 15,387 items of 24 bytes.
+struct OmegaTable {
+    OmegaItem *items = nullptr;
+    uint32_t count = 0;
+};
+static std::mutex g_omega_mu;
+static std::map<std::pair<int, int>, OmegaTable> g_omega_tables;
 
+static int omega_table(int dev, int n, uint32_t len, OmegaTable &out)
+{
+    std::lock_guard<std::mutex> lock(g_omega_mu);
+    auto it = g_omega_tables.find({dev, n});
+    if (it != g_omega_tables.end()) {
+        out = it->second;
+        return FWHT_OK;
+    }
+    const uint64_t N = (1ull << n) - 1;
     // odd primes p <= sqrt(N) by a sieve of Eratosthenes
     uint64_t root = (uint64_t)std::sqrt((double)N);
     while (root * root > N) --root;
@@ -157,31 +162,47 @@ static int omega(void *data, int dtype, int n, hipStream_t s)
     };
     std::stable_sort(items.begin(), items.end(),
                      [&](const OmegaItem &a, const OmegaItem &b) { return work(a) > work(b); });
-    if (items.size() > (size_t)kOmegaMaxItems)
-        return fail(FWHT_E_RANGE, "too many sieve items (%zu)", items.size());
-
-    // Items in stream-ordered memory: allocated, filled, read and released in
-    // the order of `s`, so concurrent calls never share them.
-    void *d_items = nullptr;
-    const size_t bytes = std::max<size_t>(items.size(), 1) * sizeof(OmegaItem);
-    e = hipMallocAsync(&d_items, bytes, s);
+    if (items.size() > (size_t)kOmegaMaxItems) return fail(FWHT_E_RANGE, "too many sieve items (%zu)", items.size());
+    OmegaTable t;
+    t.count = (uint32_t)items.size();
+    hipError_t e = hipMalloc((void **)&t.items, std::max<size_t>(items.size(), 1) * sizeof(OmegaItem));
     if (e != hipSuccess) return fail(FWHT_E_NOMEM, "prime-factor counts: %s", hipGetErrorString(e));
     if (!items.empty()) {
-        e = hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(OmegaItem), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // `items` is pageable and local
+        e = hipMemcpy(t.items, items.data(), items.size() * sizeof(OmegaItem), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(t.items);
+            return hip_fail(e, "prime-factor counts upload");
+        }
     }
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(d_items, s);
-        return hip_fail(e, "prime-factor counts upload");
-    }
+    g_omega_tables[{dev, n}] = t;
+    out = t;
+    return FWHT_OK;
+}
+
+static int omega(void *data, int dtype, int n, hipStream_t s)
+{
+    if (!data) return fail(FWHT_E_INVAL, "data is NULL");
+    if (((uintptr_t)data) & 15) return fail(FWHT_E_INVAL, "data must be 16-byte aligned");
+    if (dtype != FWHT_I32 && dtype != FWHT_I64) return fail(FWHT_E_INVAL, "dtype must be FWHT_I32 or FWHT_I64");
+    if (n < 0 || n > kOmegaMaxN) return fail(FWHT_E_RANGE, "prime-factor counts need 0 <= n <= %d", kOmegaMaxN);
+    const uint64_t total = 1ull << n;
+    const uint32_t len = (uint32_t)std::min<uint64_t>(total, kOmegaSeg);
+    const uint32_t nseg = (uint32_t)(total / len);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    const uint32_t grid = std::min<uint32_t>(nseg, (uint32_t)std::max(cus, 1) * kOmegaBlocksPerCU);
+    OmegaTable tab;
+    const int rc = omega_table(dev, n, len, tab);
+    if (rc != FWHT_OK) return rc;
     if (dtype == FWHT_I32)
-        hipLaunchKernelGGL(omega_kernel<int32_t>, dim3(grid), dim3(kOmegaThreads), 0, s, (int32_t *)data,
-                           (const OmegaItem *)d_items, (uint32_t)items.size(), nseg, len);
+        hipLaunchKernelGGL(omega_kernel<int32_t>, dim3(grid), dim3(kOmegaThreads), 0, s, (int32_t *)data, tab.items,
+                           tab.count, nseg, len);
     else
-        hipLaunchKernelGGL(omega_kernel<int64_t>, dim3(grid), dim3(kOmegaThreads), 0, s, (int64_t *)data,
-                           (const OmegaItem *)d_items, (uint32_t)items.size(), nseg, len);
+        hipLaunchKernelGGL(omega_kernel<int64_t>, dim3(grid), dim3(kOmegaThreads), 0, s, (int64_t *)data, tab.items,
+                           tab.count, nseg, len);
     e = hipGetLastError();
-    (void)hipFreeAsync(d_items, s);
     return e == hipSuccess ? FWHT_OK : hip_fail(e, "prime-factor counts launch");
 }
 

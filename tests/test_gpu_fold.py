@@ -193,3 +193,24 @@ def test_fold_planted_n40_to_2p30(O):
     direct = int(O.wht_def_at(uh, [kp])[0])
     assert k_of[k_full] == direct
     assert abs(direct) > (1 << n) // 20  # mean 2^n (1 - 2p) = 0.1 * 2^n
+
+
+def test_fold_stored_n30_bench_size(O):
+    # The stored workload of the benchmark (signs, seed 2, 2^30 int32 -> 2^24):
+    # sampled entries against direct sums over their 64 preimages, and the total.
+    n, m = 30, 24
+    x = synth.signs(1 << n, 2)
+    rows = synth.subspace_rows(n, m, 7)
+    print("fold stored n=30 m=24", flush=True)
+    xd = torch.from_numpy(x).cuda()
+    u, basis = F.fold_(xd, m, rows)
+    torch.cuda.synchronize()
+    _check_basis(rows, n, m, basis)
+    rng = np.random.default_rng(30)
+    js = [0, 1, 2, 3, (1 << m) - 1] + [int(v) for v in rng.integers(0, 1 << m, size=60)]
+    got = u[torch.tensor(js, device="cuda")].cpu().numpy()
+    for j, g in zip(js, got):
+        pre = oracle.fold_preimage(basis, n, j).astype(np.int64)
+        assert pre.size == 1 << (n - m)
+        assert int(x[pre].astype(np.int64).sum()) == int(g), j
+    assert int(u.to(torch.int64).sum().item()) == int(x.astype(np.int64).sum())

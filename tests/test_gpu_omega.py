@@ -73,3 +73,18 @@ def test_prime_omega_large(O, n):
     hits = F.fwht_int_(x, threshold=(1 << n) // 8, cap=1 << 10)
     k, v = hits.sorted()
     assert k[0] == 0 and v[0] == total
+
+
+def test_prime_omega_n32(O):
+    # The largest size (indices and prime powers up to 2^32 - 1): sampled
+    # entries, including the top of the range and squares of the largest
+    # sieving primes, against trial division; int32 output equals int64.
+    n = 32
+    x = F.prime_omega(n, dtype=torch.int32)
+    rng = np.random.default_rng(32)
+    ks = [(1 << 32) - 1, (1 << 32) - 2, (1 << 32) - 5, 65521 * 65519, 65521 * 65521 if 65521 ** 2 < 1 << 32 else 3,
+          3 ** 20, 2 ** 31, 65537 * 65519, 4294967291] + [int(v) for v in rng.integers(0, 1 << 32, 3000, dtype=np.uint64)]
+    got = x[torch.tensor(np.array(ks, dtype=np.int64), device="cuda")].cpu().numpy()
+    assert np.array_equal(got.astype(np.int64), O.prime_omega_at(ks))
+    del x
+    torch.cuda.empty_cache()
