@@ -289,8 +289,11 @@ static hipError_t launch_fold_u(const FoldArgs &a, int vb, int ub, uint32_t grid
 {
     // stored source: one 16-byte vector per step; generated source: runs of 4
     constexpr int VBMAX = (GEN || sizeof(U) == 4) ? 2 : 1;
-    if (vb == VBMAX)
+    if (vb == VBMAX) {
+        if constexpr (!GEN)
+            if (ub == 4) return launch_fold_t<U, VBMAX, 4, GEN>(a, grid, s);
         return ub ? launch_fold_t<U, VBMAX, 3, GEN>(a, grid, s) : launch_fold_t<U, VBMAX, 0, GEN>(a, grid, s);
+    }
     return ub ? launch_fold_t<U, 0, 3, GEN>(a, grid, s) : launch_fold_t<U, 0, 0, GEN>(a, grid, s);
 }
 
@@ -341,10 +344,11 @@ static int fold(const void *x, int dtype, int n, int m, const uint64_t *rows, vo
     const int nm = n - m;
     const int jb = m - vb;
     // Split each run's preimage over 2^cbits threads so that about 2^21
-    // threads run, each walking at least 8 steps of h where there are that
-    // many; a generated chunk counts its -1 entries in 32 bits.
+    // threads run, each walking at least 16 steps of h (8 for the generated
+    // source) where there are that many; a generated chunk counts its -1
+    // entries in 32 bits.
     int cb = std::max(0, 21 - jb);
-    cb = std::min(cb, std::max(0, nm - 3));
+    cb = std::min(cb, std::max(0, nm - (gen ? 3 : 4)));
     if (gen) cb = std::max(cb, nm - 31);
     cb = std::min(cb, nm);
     if (jb + cb > 38) return fail(FWHT_E_RANGE, "fold too large for one launch");
@@ -353,7 +357,8 @@ static int fold(const void *x, int dtype, int n, int m, const uint64_t *rows, vo
     a.cbits = (uint32_t)cb;
     a.lbits = (uint32_t)(nm - cb);
     a.atomic = cb > 0 ? 1u : 0u;
-    const int ub = a.lbits >= 3 ? 3 : 0;
+    // stored vectors: sixteen loads in flight per thread where h has the bits
+    const int ub = (!gen && vb > 0 && a.lbits >= 4) ? 4 : (a.lbits >= 3 ? 3 : 0);
     const uint64_t threads = 1ull << (jb + cb);
     const uint32_t grid = (uint32_t)((threads + 255) / 256);
 
