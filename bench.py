@@ -223,6 +223,22 @@ def main():
         out["cpu_parallel_fig2"] = {"value": round(N / t_par / 1e9, 5), "unit": "GElem/s", "threads": 1 << q,
                                     "seconds": round(t_par, 2)}
         del xc
+        if not args.no_extras:
+            # the oracle beside the extras, on bounded samples of their workloads
+            xs = synth.signs(1 << 24, 2)
+            rows = synth.subspace_rows(24, 18, 7)
+            t0 = time.perf_counter()
+            O.fold(xs, rows, 18)
+            t_f = time.perf_counter() - t0
+            out["subspace"]["cpu_oracle"] = {"value": round((1 << 24) / t_f / 1e9, 5), "unit": "GElem/s",
+                                             "cores": 1, "kind": "oracle",
+                                             "sample": f"stored reduction 2^24 -> 2^18 (signs, seed 2), {t_f:.2f} s"}
+            t0 = time.perf_counter()
+            O.prime_omega(1 << 26)
+            t_o = time.perf_counter() - t0
+            out["prime_omega"]["cpu_oracle"] = {"value": round((1 << 26) / t_o / 1e9, 5), "unit": "GElem/s",
+                                                "cores": 1, "kind": "oracle",
+                                                "sample": f"Omega(i) for i < 2^26 (sieve + division), {t_o:.2f} s"}
     print(json.dumps(out), flush=True)
 
 
