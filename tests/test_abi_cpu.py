@@ -143,3 +143,18 @@ def test_prime_omega_validation(L):
     assert L.fwht_prime_omega(C.c_void_p(p), 2, 10, None) == _lib.FWHT_E_INVAL
     assert L.fwht_prime_omega(C.c_void_p(p), 1, 33, None) == _lib.FWHT_E_RANGE
     assert L.fwht_prime_omega(C.c_void_p(p), 1, -1, None) == _lib.FWHT_E_RANGE
+
+
+def test_missing_library_fails_loudly():
+    # With the HIP library absent the binding raises; there is no CPU fallback.
+    import subprocess, sys
+    code = ("import paper_1607_01039_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/libfwht.so'\n"
+            "L._lib = None\n"
+            "try:\n"
+            "    L.lib()\n"
+            "except ImportError as e:\n"
+            "    assert 'missing' in str(e)\n"
+            "else:\n"
+            "    raise SystemExit('no error')\n")
+    subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
