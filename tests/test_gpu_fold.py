@@ -214,3 +214,25 @@ def test_fold_stored_n30_bench_size(O):
         assert pre.size == 1 << (n - m)
         assert int(x[pre].astype(np.int64).sum()) == int(g), j
     assert int(u.to(torch.int64).sum().item()) == int(x.astype(np.int64).sum())
+
+
+def test_fold_planted_n44(O):
+    # 2^44 generated entries (about 11 s) reduced to 2^30: each thread walks
+    # 2^14 steps of h; sampled entries against direct sums over their 2^14
+    # preimages, and the entry holding the planted peak's coefficient.
+    n, m, p, seed = 44, 30, 0.45, 8
+    mask, state, thr = synth.planted_params(n, seed, p)
+    rows = synth.subspace_rows(n, m, 44)
+    rows[0] = np.uint64(mask)
+    assert oracle.gf2_rank(rows) == m
+    print("fold planted n=44 m=30", flush=True)
+    u, basis = F.fold_planted(n, m, rows, mask, state, thr, dtype=torch.int32)
+    torch.cuda.synchronize()
+    _check_basis(rows, n, m, basis)
+    rng = np.random.default_rng(44)
+    js = [0, (1 << m) - 1] + [int(v) for v in rng.integers(0, 1 << m, size=6)]
+    got = u[torch.tensor(js, device="cuda")].cpu().numpy()
+    for j, g in zip(js, got):
+        pre = oracle.fold_preimage(basis, n, j)
+        assert pre.size == 1 << (n - m)
+        assert int(synth.planted_at(n, seed, p, pre).sum()) == int(g), j
