@@ -23,8 +23,8 @@
 // thread of a wave, so its low VB bits only permute the vector (a
 // wave-uniform selection) and its other bits move the whole wave to another
 // run: every load is coalesced.  h is walked in Gray-code order (one gamma
-// per step), with the low three bits of h unrolled so that eight loads are
-// in flight per thread.
+// per step), with its low four bits unrolled for a stored signal (sixteen
+// loads in flight per thread) and its low three bits for a generated one.
 //
 // Two sources: a signal stored in device memory (bound by HBM: 2^n reads and
 // 2^m writes), and the planted signal of the synthetic inputs generated on
