@@ -81,9 +81,14 @@ __global__ void __launch_bounds__(kOmegaThreads, kOmegaBlocksPerCU * kOmegaThrea
                 int64_t rr = (int64_t)L - (int64_t)qe * m.q;
                 rr = rr < 0 ? rr + m.q : (rr >= (int64_t)m.q ? rr - m.q : rr);
                 const uint64_t f = rr ? (uint64_t)(m.q - rr) : 0ull;  // first multiple of q at or after L
-                const uint64_t step = (uint64_t)m.cs * m.q;
-                for (uint64_t j = f + (uint64_t)m.c0 * m.q; j < len; j += step)
-                    atomicAdd(&seg[(uint32_t)j >> 1], m.w << (((uint32_t)j & 1u) * 16u));
+                const uint64_t j0 = f + (uint64_t)m.c0 * m.q;
+                if (j0 < len) {
+                    // 32-bit walk: j < 2^15 and a step of len or more leaves the segment
+                    const uint64_t step64 = (uint64_t)m.cs * m.q;
+                    const uint32_t step = step64 < len ? (uint32_t)step64 : len;
+                    for (uint32_t j = (uint32_t)j0; j < len; j += step)
+                        atomicAdd(&seg[j >> 1], m.w << ((j & 1u) * 16u));
+                }
             }
         }
         __syncthreads();
