@@ -10,9 +10,10 @@
 // base-2 logarithms in units of 1/32 (below 2048 because i < 2^32), so an
 // entry never carries into its neighbour.  The factor 2 comes from the
 // trailing zeros of i.  What is left of i after the sieved factors is 1 or a
-// single prime above sqrt(N) (two such primes would exceed N); it is at least
-// 3, so it shows as a logarithm gap of at least log2(3) = 1.58 between log2(i)
-// and the sum, while the rounding of the sum stays below 20 / 64 = 0.31: a gap
+// single prime: one above sqrt(N) (two would exceed N), or one above the cube
+// root of N whose square is not sieved (see the table); it is at least 3, so
+// it shows as a logarithm gap of at least log2(3) = 1.58 between log2(i) and
+// the sum, while the rounding of the sum stays below 20 / 64 = 0.31: a gap
 // above 0.8 adds the last factor.
 //
 // Load balance: the multiples of q in a segment are dealt to C = ceil(count / 32)
@@ -151,11 +152,18 @@ static int omega_table(int dev, int n, uint32_t len, OmegaTable &out)
         if (comp[p]) continue;
         for (uint64_t j = p * p; j <= root; j += 2 * p) comp[j] = 1;
         const uint32_t w = (1u << 11) + (uint32_t)std::lround(std::log2((double)p) * 32.0);
-        for (uint64_t q = p; q <= N; q *= p) {
-            const uint64_t per_seg = (len + q - 1) / q;  // most multiples of q in one segment
-            const uint64_t chunks = (per_seg + kOmegaChunk - 1) / kOmegaChunk;
-            for (uint64_t c = 0; c < chunks; ++c)
-                items.push_back(OmegaItem{(uint32_t)q, w, (uint32_t)c, (uint32_t)chunks, 1.0 / (double)q});
+        // The square of a prime above the cube root of N is left out: such a p
+        // divides i at most twice (p^3 > N), and where it does, nothing above
+        // sqrt(N) divides i too (p^2 P > N), so the one factor p left over is
+        // counted by the logarithm gap like a prime above sqrt(N).
+        const bool skip_square = p > N / p / p;
+        for (uint64_t q = p, k = 1; q <= N; q *= p, ++k) {
+            if (!(k == 2 && skip_square)) {
+                const uint64_t per_seg = (len + q - 1) / q;  // most multiples of q in one segment
+                const uint64_t chunks = (per_seg + kOmegaChunk - 1) / kOmegaChunk;
+                for (uint64_t c = 0; c < chunks; ++c)
+                    items.push_back(OmegaItem{(uint32_t)q, w, (uint32_t)c, (uint32_t)chunks, 1.0 / (double)q});
+            }
             if (q > N / p) break;
         }
     }
