@@ -30,7 +30,7 @@ PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
 
 __all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
            "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
-           "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "prime_omega",
+           "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "subspace_scan", "prime_omega",
            "FWHTError", "PRECISIONS"]
 
 
@@ -213,6 +213,36 @@ def subspace_transform(u, basis, threshold, cap: int = 1 << 16, hits=None) -> Hi
     subspace_hits_(bufs, basis)
     _torch().cuda.current_stream().synchronize()
     return _collect(*bufs, cap)
+
+
+def subspace_scan(source, m: int, rows_list, threshold, cap: int = 1 << 16, dtype=None):
+    """Section 5.1's scheme of independent reductions (one per machine in the
+    paper) run one after another on this GPU: each rank-m reduction in
+    ``rows_list`` (caller-drawn rows) of the same signal is transformed and
+    thresholded, and the hits are merged by full-space index.
+
+    ``source`` is a stored signal (1-D int32/int64 CUDA tensor) or the planted
+    signal's parameters ``(n, mask, state, thr)`` generated on the fly.
+    Returns ``(hits, bases)``: a dict {index: coefficient} of every coefficient
+    above ``threshold`` on the union of the subspaces, and the canonical basis
+    of each reduction (the subspaces it covered)."""
+    torch = _torch()
+    out, bufs, hits, bases = None, None, {}, []
+    for rows in rows_list:
+        if isinstance(source, tuple):
+            n, mask, state, thr = source
+            out, basis = fold_planted(n, m, rows, mask, state, thr, dtype=dtype, out=out)
+        else:
+            out, basis = fold_(source, m, rows, out=out)
+        if bufs is None:
+            bufs = hit_buffers(out, cap)
+        h = subspace_transform(out, basis, threshold, hits=bufs)
+        if h.overflow:
+            raise FWHTError(_lib.FWHT_E_CAPACITY, f"{h.count} hits exceed the capacity {cap}")
+        for k, v in zip(h.idx.tolist(), h.val.tolist()):
+            hits[int(k)] = int(v)
+        bases.append(basis)
+    return hits, bases
 
 
 def prime_omega(n: int, dtype=None, out=None, device="cuda"):

@@ -236,3 +236,25 @@ def test_fold_planted_n44(O):
         pre = oracle.fold_preimage(basis, n, j)
         assert pre.size == 1 << (n - m)
         assert int(synth.planted_at(n, seed, p, pre).sum()) == int(g), j
+
+
+def test_subspace_scan_union(O):
+    # Section 5.1's scheme at a scale the oracle can check: 64 independent
+    # reductions of 2^20 planted entries to 2^15 (1/32 of the coefficients
+    # each, as in the paper's example).  The merged hits equal the oracle's
+    # coefficients above T on the union of the 64 subspaces, and that union
+    # covers close to 1 - (31/32)^64 = 87% of the spectrum.
+    n, m, R, p, seed = 20, 15, 64, 0.45, 9
+    mask, state, thr = synth.planted_params(n, seed, p)
+    rows_list = [synth.subspace_rows(n, m, 700 + r) for r in range(R)]
+    T = int(np.ceil(4 * 2 ** (n / 2)))
+    hits, bases = F.subspace_scan((n, mask, state, thr), m, rows_list, T)
+    x, s, _ = synth.planted(n, seed, p, dtype=np.int64)
+    W = O.wht_fig1(x)
+    covered = np.zeros(1 << n, dtype=bool)
+    for b in bases:
+        covered[O.subspace_indices(b, range(1 << m)).astype(np.int64)] = True
+    want = {int(k): int(W[k]) for k in np.flatnonzero(covered & (np.abs(W) > T))}
+    assert hits == want
+    share = covered.mean()
+    assert abs(share - (1 - (31 / 32) ** R)) < 0.02, share
