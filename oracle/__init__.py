@@ -91,8 +91,12 @@ class Oracle:
         L.fold_u32.argtypes = [_u32p, C.c_int, _u64p, C.c_int, _u32p]
         L.subspace_index.argtypes = [_u64p, C.c_int, C.c_uint64]
         L.subspace_index.restype = C.c_uint64
-        L.prime_omega.argtypes = [C.c_uint64, _i32p]
+        L.prime_omega.argtypes = [C.c_uint64, _i32p, C.c_int]
         L.prime_omega.restype = C.c_int
+        L.kf_sum.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint64, C.c_int, _u64p, C.c_int, C.c_int]
+        L.kf_sum.restype = C.c_uint64
+        L.sumsq_mod.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_int, C.c_int]
+        L.sumsq_mod.restype = C.c_uint64
         L.prime_omega_at.argtypes = [C.c_uint64]
         L.prime_omega_at.restype = C.c_int32
 
@@ -264,17 +268,54 @@ class Oracle:
         return np.array([self.subspace_index(rows, k) for k in kps], dtype=np.uint64)
 
     # ---- prime-factor counts (the workload announced in section 4.3) --------
-    def prime_omega(self, count: int) -> np.ndarray:
+    def prime_omega(self, count: int, threads: int | None = None) -> np.ndarray:
         """Omega(i) (prime factors with multiplicity; Omega(0) = Omega(1) = 0)
-        for i in [0, count), int32."""
+        for i in [0, count), int32, on `threads` host threads."""
         out = np.empty(max(count, 1), dtype=np.int32)
-        if self._L.prime_omega(count, out) != 0:
+        if self._L.prime_omega(count, out, threads or host_threads()) != 0:
             raise MemoryError("prime_omega")
         return out[:count]
 
     def prime_omega_at(self, ks) -> np.ndarray:
         """Omega(k) of single numbers by trial division."""
         return np.array([self._L.prime_omega_at(int(k)) for k in ks], dtype=np.int64)
+
+
+    # ---- checks of transforms too large to keep an oracle copy of ------------
+    KF_P = (1 << 61) - 1
+
+    def kf_sum(self, data: np.ndarray, n: int, t, side: int, start: int = 0,
+               threads: int | None = None) -> int:
+        """sum_i data[i] * w(start + i) mod P = 2^61 - 1, for a slice of a
+        transform of 2^n entries: side 0 weighs the output index k by
+        prod_j t_j^(bit j of k), side 1 the input index i by
+        prod_j (1 + (-1)^(bit j of i) t_j).  For a correct transform the two
+        sides agree (H is symmetric); see ``kf_sum`` in wht_oracle.c."""
+        data = np.ascontiguousarray(data)
+        if data.dtype not in (np.int32, np.int64):
+            raise TypeError(data.dtype)
+        tv = np.ascontiguousarray(np.asarray(t, dtype=np.uint64))
+        if tv.size < n:
+            raise ValueError("t needs n entries")
+        r = self._L.kf_sum(data.ctypes.data_as(C.c_void_p), data.itemsize, int(start), data.size, int(n), tv,
+                           int(side), threads or host_threads())
+        if r == (1 << 64) - 1:
+            raise ValueError("kf_sum: bad arguments")
+        return int(r)
+
+    def sumsq(self, data: np.ndarray, mod_p: bool = False, threads: int | None = None) -> int:
+        """sum of data[i]^2 mod 2^64 (wrap-around), or mod P = 2^61 - 1."""
+        data = np.ascontiguousarray(data)
+        if data.dtype not in (np.int32, np.int64):
+            raise TypeError(data.dtype)
+        return int(self._L.sumsq_mod(data.ctypes.data_as(C.c_void_p), data.itemsize, data.size, int(bool(mod_p)),
+                                     threads or host_threads()))
+
+
+def host_threads() -> int:
+    """Threads the multi-threaded oracle functions use: the host's cores, at
+    most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 # ---- GF(2) linear algebra for section 5.1 (plain Gaussian elimination) ------

@@ -16,7 +16,12 @@ oracle disagrees with something other than itself:
   k, true count beyond the capacity);
 * the orthonormal scale 2^(-n/2) and the gradient of a weighted square loss,
   checked by central finite differences (exact for a quadratic up to
-  rounding).
+  rounding);
+* the checks used where no oracle copy of a transform fits: the randomized
+  identity sum_k W_k w_k = sum_i x_i (H w)_i for Kronecker-product weights
+  (mod 2^61 - 1) and Parseval's identity mod 2^64 and mod 2^61 - 1, against
+  the Fig. 1 transform, corrupted transforms and sums written out over
+  Python integers.
 
 The mutation test runs every pin against builds of the oracle with a planted
 mistake and requires each such build to fail at least one pin.
@@ -415,6 +420,101 @@ def pin_omega_additive_and_legendre(O):
     for (x, k) in ((1 << 30, 30), (3 ** 18, 18), (int(ps[-1]) * int(ps[-2]), 2),
                    (int(ps[-1]) * int(ps[100]) * 4, 4), (int(ps[-1]) ** 2, 2), (int(ps[-1]), 1)):
         assert O.prime_omega_at([x])[0] == k, x
+
+
+def pin_omega_threads(O):
+    # The sieve splits the index range over threads: the result must not
+    # depend on how (ragged parts, more threads than small primes), and a
+    # range that ends just past a square of a prime keeps that square's count.
+    for count in (2, 3, 50, 10007, 1 << 17):
+        ref = O.prime_omega(count, threads=1)
+        for th in (2, 3, 7, 16):
+            assert np.array_equal(O.prime_omega(count, threads=th), ref), (count, th)
+    assert O.prime_omega(122, threads=5)[121] == 2 and O.prime_omega(10202, threads=9)[10201] == 2
+
+
+# ---- checks for transforms too large to keep an oracle copy of -------------
+
+_KF_P = (1 << 61) - 1
+
+
+def _kf_brute(y, n, t, side):
+    """sum_k y_k w_side(k) mod P written out over Python integers."""
+    acc = 0
+    for k in range(1 << n):
+        w = 1
+        for j in range(n):
+            bit = (k >> j) & 1
+            if side == 0:
+                w = w * (t[j] if bit else 1) % _KF_P
+            else:
+                w = w * ((1 - t[j]) if bit else (1 + t[j])) % _KF_P
+        acc = (acc + int(y[k]) * w) % _KF_P
+    return acc
+
+
+def pin_kf_identity(O):
+    # sum_k W_k prod_j t_j^(k_j) = sum_i x_i prod_j (1 + (-1)^(i_j) t_j) (mod P)
+    # holds for the transform (Fig. 1) and for no plausible corruption of it.
+    rng = np.random.default_rng(17)
+    for n in (0, 1, 5, 12, 18):
+        N = 1 << n
+        x = synth.ints(N, 700 + n, -(1 << 40), 1 << 40)
+        W = O.wht_fig1(x)
+        for trial in range(2):
+            t = [int(v) for v in rng.integers(0, _KF_P, size=max(n, 1), dtype=np.uint64)]
+            lhs, rhs = O.kf_sum(W, n, t, 0), O.kf_sum(x, n, t, 1)
+            assert lhs == rhs, (n, trial)
+            if n >= 1:
+                bad = W.copy(); bad[N // 3] += 1
+                assert O.kf_sum(bad, n, t, 0) != rhs, n
+                bad = W.copy(); bad[[0, N - 1]] = bad[[N - 1, 0]]
+                assert W[0] == W[N - 1] or O.kf_sum(bad, n, t, 0) != rhs, n
+                assert O.kf_sum(-W, n, t, 0) != rhs, n
+            if n >= 2:
+                rev = np.array([int(format(k, f"0{n}b")[::-1], 2) for k in range(N)])
+                assert O.kf_sum(W[rev], n, t, 0) != rhs, n
+    # int32 data, and sums taken chunk by chunk at arbitrary boundaries
+    n = 16
+    x = synth.signs(1 << n, 71)
+    W = O.wht_fig1(x)
+    t = [int(v) for v in rng.integers(0, _KF_P, size=n, dtype=np.uint64)]
+    whole = O.kf_sum(W, n, t, 0)
+    cuts = [0, 1, 4097, 30000, 1 << n]
+    parts = sum(O.kf_sum(W[a:b], n, t, 0, start=a) for a, b in zip(cuts[:-1], cuts[1:])) % _KF_P
+    assert parts == whole == O.kf_sum(x, n, t, 1)
+    assert O.kf_sum(W, n, t, 0, threads=1) == O.kf_sum(W, n, t, 0, threads=13) == whole
+
+
+def pin_kf_brute_force(O):
+    # The C sums against the weights written out over Python integers
+    # (extreme residues of t included), on transformed and untransformed data.
+    rng = np.random.default_rng(5)
+    for n in (1, 3, 6):
+        x = synth.ints(1 << n, 800 + n, -(1 << 62), 1 << 62)
+        x[0] = np.iinfo(np.int64).min
+        for t in ([0] * n, [_KF_P - 1] * n, [int(v) for v in rng.integers(0, _KF_P, size=n, dtype=np.uint64)]):
+            for side in (0, 1):
+                assert O.kf_sum(x, n, t, side) == _kf_brute(x, n, t, side), (n, side)
+
+
+def pin_parseval_mod(O):
+    # Parseval (section 2): sum_k W_k^2 = 2^n sum_i x_i^2, exact in Python
+    # integers and then reduced mod 2^64 and mod P; a one-unit error in any
+    # coefficient changes the sum by 2 W_k + 1, an odd number.
+    for n in (0, 3, 12, 17):
+        N = 1 << n
+        x = synth.ints(N, 900 + n, -(1 << 20), 1 << 20)
+        W = O.wht_fig1(x)
+        exact = sum(int(v) * int(v) for v in x.tolist()) * N
+        assert O.sumsq(W) == exact % (1 << 64), n
+        assert O.sumsq(W, mod_p=True) == exact % _KF_P, n
+        assert O.sumsq(x.astype(np.int32), mod_p=True) == (exact // N) % _KF_P, n
+        bad = W.copy(); bad[N - 1] += 1
+        assert O.sumsq(bad) != exact % (1 << 64), n
+    big = np.array([np.iinfo(np.int64).min, -3, (1 << 40) + 7], dtype=np.int64)
+    ex = sum(int(v) * int(v) for v in big.tolist())
+    assert O.sumsq(big) == ex % (1 << 64) and O.sumsq(big, mod_p=True) == ex % _KF_P
 
 
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_") and k != "pin_subspace_coverage_example"]

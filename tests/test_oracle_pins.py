@@ -25,8 +25,12 @@ def test_pin(O, pin):
 # gap at bit k, 12 rows of the reduction map applied in reverse order, 13 OR
 # instead of XOR when mapping a reduced index back to the full space, 14 a
 # square factor 2^2 counted once in the prime-factor counts, 15 the last prime
-# factor above the square root dropped by trial division.
-MUTANTS = list(range(1, 16))
+# factor above the square root dropped by trial division, 16 the signs of the
+# input-side weights of the randomized transform check swapped, 17 a negative
+# entry reduced mod 2^61 - 1 as if unsigned, 18 the check's random point
+# ignored (every weight collapses onto index 0), 19 the last entry of each
+# thread's part left out of the Parseval sums.
+MUTANTS = list(range(1, 20))
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
