@@ -106,10 +106,12 @@ int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void 
  *   data    : device FP32 buffer; transform t occupies
  *             data[offsets[t] .. offsets[t] + 2^log2n[t]).
  *   offsets : HOST array [count] of entry offsets (each a multiple of 4).
- *   log2n   : HOST array [count], each in [0, 16].
+ *   log2n   : HOST array [count], each in [2, 16] (FWHT_E_RANGE otherwise).
  * The work list is built from the host arrays on the first call with a given
  * (data, count, normalize, prec, contents of offsets/log2n) and cached with
- * its graph; later identical calls only replay the graph on `stream`.
+ * its graph, together with a copy of both arrays; a later call whose
+ * arguments equal a cached request element for element only replays that
+ * graph on `stream`.
  * Transforms must not overlap.  Errors: FWHT_E_INVAL, FWHT_E_RANGE,
  * FWHT_E_NOMEM, FWHT_E_HIP.  Not thread-safe with itself. */
 int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,

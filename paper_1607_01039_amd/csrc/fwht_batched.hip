@@ -30,6 +30,8 @@ struct Plan {
     int32_t count = 0;
     int normalize = 0, prec = 0;
     uint64_t hash = 0;
+    std::vector<int64_t> off;  // the request itself, compared on a hash match
+    std::vector<int32_t> lg;
     // device state
     BItem *items = nullptr;
     int64_t *segs = nullptr;
@@ -45,7 +47,9 @@ hipStream_t g_capture = nullptr;
 
 // Cache key of the host arrays: a multiply-xorshift hash over 8-byte words
 // (a byte-wise hash of 4096 offsets and sizes took tens of microseconds,
-// spent on the host before every replay).
+// spent on the host before every replay).  A plan matches only when the
+// hash and then the stored arrays themselves are equal, so a collision can
+// never replay another request's graph.
 uint64_t hash_words(const void *p, size_t n, uint64_t h)
 {
     const unsigned char *c = (const unsigned char *)p;
@@ -169,7 +173,8 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
     auto it = g_plans.begin();
     for (; it != g_plans.end(); ++it)
         if (it->data == data && it->count == count && it->normalize == normalize && it->prec == prec &&
-            it->hash == h)
+            it->hash == h && !memcmp(it->off.data(), off, sizeof(int64_t) * (size_t)count) &&
+            !memcmp(it->lg.data(), lg, sizeof(int32_t) * (size_t)count))
             break;
     if (it == g_plans.end()) {
         if (g_plans.size() >= kMaxPlans) {
@@ -185,6 +190,8 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
         p.normalize = normalize;
         p.prec = prec;
         p.hash = h;
+        p.off.assign(off, off + count);
+        p.lg.assign(lg, lg + count);
         int rc = make_plan(p, data, off, lg, count, normalize, prec);
         if (rc) {
             release(p);

@@ -200,6 +200,17 @@ def planted(n: int, seed: int, p: float, dtype=np.int32, start: int = 0,
     return out, s, int(errors)
 
 
+def raw64(count: int, seed: int, out: np.ndarray | None = None) -> np.ndarray:
+    """Full-range int64 values: the SplitMix64 outputs of stream 3, read as
+    two's-complement (every bit of a 64-bit word random, so transforms of
+    them wrap around mod 2^64 at every size)."""
+    if out is None:
+        out = np.empty(count, dtype=np.int64)
+    assert out.size == count and out.dtype == np.int64 and out.flags.c_contiguous
+    _clib().synth_splitmix64(stream_state(seed, 3), 0, count, out.ctypes.data_as(C.c_void_p))
+    return out
+
+
 def normal(shape, seed: int) -> np.ndarray:
     """i.i.d. N(0,1) float32 (numpy PCG64)."""
     return np.random.Generator(np.random.PCG64(seed)).standard_normal(shape, dtype=np.float32)

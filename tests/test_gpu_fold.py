@@ -10,11 +10,19 @@ import pytest
 import torch
 
 import oracle
+import paper_1607_01039_amd as F  # an import failure fails collection, never skips
 import synth
 
 pytestmark = pytest.mark.gpu
 
-F = pytest.importorskip("paper_1607_01039_amd")
+
+@pytest.fixture(scope="module", autouse=True)
+def _native_library():
+    """Every test here runs the HIP library: load it or fail."""
+    assert torch.cuda.is_available()
+    F._lib.lib()
+
+
 TORCH = {np.int32: torch.int32, np.int64: torch.int64}
 
 

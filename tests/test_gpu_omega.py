@@ -5,10 +5,15 @@ import pytest
 import torch
 
 import oracle
+import paper_1607_01039_amd as F  # an import failure fails collection, never skips
 
 pytestmark = pytest.mark.gpu
 
-F = pytest.importorskip("paper_1607_01039_amd")
+@pytest.fixture(scope="module", autouse=True)
+def _native_library():
+    """Every test here runs the HIP library: load it or fail."""
+    assert torch.cuda.is_available()
+    F._lib.lib()
 
 
 @pytest.fixture(scope="module")

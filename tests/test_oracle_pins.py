@@ -67,6 +67,8 @@ def test_synth_c_matches_definition(n, seed, p, start):
         b = synth.planted_ref(n, seed, p, dtype=dt, start=start, count=cnt)
         assert np.array_equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
     assert np.array_equal(synth.signs(1000, seed), synth.signs_ref(1000, seed))
+    raw = synth.raw64(1000, seed)
+    assert np.array_equal(raw.view(np.uint64), synth.splitmix64(synth.stream_state(seed, 3), 0, 1000))
 
 
 def test_planted_noise_statistics(O):
