@@ -287,31 +287,101 @@ def test_copy_kernel(F, nbytes):
     assert torch.equal(dst, src)
 
 
+# ---- the tuned default schedules, element by element --------------------------
+#
+# Every size from 2^13 entries up runs the schedule of the tuned table
+# (tune/gfx950.txt) unless a test overrides it; these tests run that default
+# at every such size and compare every entry with the oracle's Fig. 2 (16
+# host threads), so that a retuned table cannot change a result unnoticed.
+
+def _tuned_table():
+    import os
+    import paper_1607_01039_amd as F
+    path = os.path.join(os.path.dirname(F.__file__), "tune", "gfx950.txt")
+    tab = {}
+    for ln in open(path):
+        f = ln.split()
+        if f and not ln.startswith("#"):
+            tab[(f[0], int(f[1]))] = f[2]
+    return tab
+
+
+CHUNK = 1 << 27  # entries per host <-> device copy and per comparison
+
+
+def _upload(x):
+    import torch
+    t = torch.empty(x.size, dtype=torch.from_numpy(x[:1]).dtype, device="cuda")
+    for c0 in range(0, x.size, CHUNK):
+        t[c0:c0 + CHUNK].copy_(torch.from_numpy(x[c0:c0 + CHUNK]))
+    return t
+
+
+def _equal_chunks(t, ref):
+    """Device tensor t equals the host array ref entry for entry (chunked, so
+    no second full-size host copy is made); returns the first bad chunk."""
+    for c0 in range(0, ref.size, CHUNK):
+        if not np.array_equal(t[c0:c0 + CHUNK].cpu().numpy(), ref[c0:c0 + CHUNK]):
+            return c0
+    return None
+
+
+def _default_schedule_parity(F, O, dtype_name, n, x):
+    import torch
+    tab = _tuned_table()
+    if (dtype_name, n) in tab:
+        assert F.get_schedule(dtype_name, n) == tab[(dtype_name, n)]
+    print(f"{dtype_name} n={n} schedule {F.get_schedule(dtype_name, n)}", flush=True)
+    t = _upload(x)
+    F.fwht_int_(t)
+    torch.cuda.synchronize()
+    O.wht_fig2_inplace(x, 4)  # x becomes the expected transform
+    bad = _equal_chunks(t, x)
+    del t
+    torch.cuda.empty_cache()
+    assert bad is None, f"first differing chunk at entry {bad}"
+
+
+@pytest.mark.parametrize("n", list(range(23, 30)))
+def test_int32_default_schedule(F, O, n):
+    # full-range int32 values: every entry wraps mod 2^32
+    x = synth.ints(1 << n, 4000 + n, -(1 << 31), (1 << 31) - 1, dtype=np.int32)
+    _default_schedule_parity(F, O, "int32", n, x)
+
+
+@pytest.mark.parametrize("n", list(range(13, 33)))
+def test_int64_default_schedule(F, O, n):
+    # full-range int64 values (every bit random): every entry wraps mod 2^64;
+    # n = 32 is 32 GiB on each side
+    x = synth.raw64(1 << n, 4100 + n)
+    _default_schedule_parity(F, O, "int64", n, x)
+
+
 @pytest.mark.parametrize("n", [33, 34])
 def test_int64_large_in_hbm(F, O, n):
     """int64 up to the in-HBM limit (n = 34: 128 GiB resident), planted peak
-    (seed 3, p = 0.48), fused threshold T = ceil(6 * 2^(n/2)): the peak in
-    closed form, the definition at the peak, at a hit and at a random k, and
-    the involution H(Hx) = 2^n x checked on every entry."""
+    (seed 3, p = 0.48), fused threshold T = ceil(6 * 2^(n/2)): every entry
+    against the oracle's Fig. 2 run in place on the host copy of the input,
+    the hit set against the oracle's threshold scan, and the peak in closed
+    form."""
     import math
     import torch
     N = 1 << n
     T = int(math.ceil(6 * 2 ** (n / 2)))
+    print(f"int64 in HBM n={n}: generating", flush=True)
     x, s, err = synth.planted(n, 3, 0.48, dtype=np.int64)
-    t = torch.empty(N, dtype=torch.int64, device="cuda")
-    C = 1 << 28
-    for c0 in range(0, N, C):
-        t[c0:c0 + C].copy_(torch.from_numpy(x[c0:c0 + C]))
+    t = _upload(x)
+    print("transforming", flush=True)
     hits = F.fwht_int_(t, threshold=T, cap=1 << 12)
     assert int(t[s].item()) == N - 2 * err
-    gi, gv = hits.sorted()
-    assert s in set(gi.tolist()) and hits.count <= (1 << 12)
-    other = [k for k in gi.tolist() if k != s][:1]
-    ks = [s] + other + [int(np.random.default_rng(n).integers(0, N))]
-    got = t[torch.tensor(ks, device="cuda")].cpu().numpy()
-    assert np.array_equal(O.wht_def_at(x, ks), got)
-    F.fwht_int_(t)
-    for c0 in range(0, N, C):
-        assert torch.equal(t[c0:c0 + C], torch.from_numpy(x[c0:c0 + C]).cuda() * N), c0
+    print("oracle (Fig. 2, 16 threads)", flush=True)
+    O.wht_fig2_inplace(x, 4)
+    print("comparing", flush=True)
+    bad = _equal_chunks(t, x)
     del t
     torch.cuda.empty_cache()
+    assert bad is None, f"first differing chunk at entry {bad}"
+    ridx, rval, rcnt = O.threshold(x, T, cap=1 << 12)
+    gi, gv = hits.sorted()
+    assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+    assert s in set(gi.tolist())

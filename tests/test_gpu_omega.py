@@ -80,6 +80,20 @@ def test_prime_omega_large(O, n):
     assert k[0] == 0 and v[0] == total
 
 
+def test_prime_omega_n30_every_entry(O):
+    # The benchmark size: all 2^30 entries (int64 on the device) against the
+    # oracle's sieve, chunk by chunk.
+    n, C = 30, 1 << 26
+    print("prime omega n=30 (every entry)", flush=True)
+    x = F.prime_omega(n)
+    ref = O.prime_omega(1 << n)
+    for c0 in range(0, 1 << n, C):
+        got = x[c0:c0 + C].cpu().numpy()
+        assert np.array_equal(got, ref[c0:c0 + C].astype(np.int64)), c0
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_prime_omega_n32(O):
     # The largest size (indices and prime powers up to 2^32 - 1): sampled
     # entries, including the top of the range and squares of the largest
