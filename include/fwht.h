@@ -117,6 +117,24 @@ int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void 
 int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
                  int normalize, int prec, void *stream);
 
+/* Largest `count` of fwht_batched_noalloc. */
+#define FWHT_NOALLOC_MAX_TRANSFORMS 65536
+
+/* fwht_batched for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors as fwht_batched, plus FWHT_E_RANGE
+ * when count > FWHT_NOALLOC_MAX_TRANSFORMS.  It calls no allocating routine:
+ * the work list is built in host memory of the library and copied, ordered
+ * on `stream`, into a fixed device array of the library ((16 + 8) *
+ * FWHT_NOALLOC_MAX_TRANSFORMS bytes = 1.5 MiB, one per GPU, held until the
+ * process ends), and the persistent kernel is launched directly on `stream`
+ * (no graph, no plan cache).  The call returns once the work list has left
+ * host memory.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (different streams, or threads, with no ordering between them)
+ * race on it, and the caller must order them. */
+int fwht_batched_noalloc(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
+                         int normalize, int prec, void *stream);
+
 /* Stand-alone threshold pass over 2^n already-transformed device entries of
  * dtype `dtype` (I32/I64 compare |W_k| > th->T exactly in 64 bits; F32
  * compares |W_k| > th->Tf).  *th->count is zeroed by the call and receives

@@ -28,7 +28,7 @@ from ._lib import FWHTError
 PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
               "bf16": _lib.FWHT_PREC_BF16_MFMA}
 
-__all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "threshold", "fwht", "FWHTFunction",
+__all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "fwht_batched_noalloc_", "threshold", "fwht", "FWHTFunction",
            "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
            "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "subspace_scan", "prime_omega",
            "FWHTError", "PRECISIONS"]
@@ -287,6 +287,20 @@ def fwht_batched_(data, offsets, log2n, normalize: bool = True, precision: str =
     _lib.check(_lib.lib().fwht_batched(C.c_void_p(data.data_ptr()), off.ctypes.data_as(C.c_void_p),
                                        lg.ctypes.data_as(C.c_void_p), len(off), int(bool(normalize)),
                                        PRECISIONS[precision], _stream_ptr(data)))
+    return data
+
+
+def fwht_batched_noalloc_(data, offsets, log2n, normalize: bool = True, precision: str = "fp32"):
+    """``fwht_batched_`` through the entry point that allocates nothing (a
+    fixed work-list array of the library per GPU; at most 65536 transforms;
+    calls on one GPU must not overlap)."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+    if off.shape != lg.shape:
+        raise ValueError("offsets and log2n must have the same length")
+    _lib.check(_lib.lib().fwht_batched_noalloc(C.c_void_p(data.data_ptr()), off.ctypes.data_as(C.c_void_p),
+                                               lg.ctypes.data_as(C.c_void_p), len(off), int(bool(normalize)),
+                                               PRECISIONS[precision], _stream_ptr(data)))
     return data
 
 

@@ -14,12 +14,13 @@ LIB_PATH = os.path.join(PKG, "libfwht.so")
 FWHT_OK, FWHT_E_INVAL, FWHT_E_RANGE, FWHT_E_CAPACITY, FWHT_E_NOMEM, FWHT_E_HIP, FWHT_E_UNSUPPORTED = range(7)
 FWHT_I32, FWHT_I64, FWHT_F32 = 0, 1, 2
 FWHT_PREC_FP32, FWHT_PREC_FP16_MFMA, FWHT_PREC_BF16_MFMA = 0, 1, 2
+FWHT_NOALLOC_MAX_TRANSFORMS = 65536
 
 STATUS_NAMES = {0: "FWHT_OK", 1: "FWHT_E_INVAL", 2: "FWHT_E_RANGE", 3: "FWHT_E_CAPACITY",
                 4: "FWHT_E_NOMEM", 5: "FWHT_E_HIP", 6: "FWHT_E_UNSUPPORTED"}
 
 # Every symbol include/fwht.h declares.
-EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
+EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
            "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_trace_enable", "fwht_trace_read",
            "fwht_copy", "fwht_fold", "fwht_fold_planted", "fwht_subspace_hits", "fwht_prime_omega", "fwht_last_error",
            "fwht_version")
@@ -56,6 +57,7 @@ def lib() -> C.CDLL:
     L.fwht_int.argtypes = [vp, i32, i32, C.POINTER(fwht_thresh_t), vp]
     L.fwht_float.argtypes = [vp, i32, i64, i32, i32, vp]
     L.fwht_batched.argtypes = [vp, vp, vp, C.c_int32, i32, i32, vp]
+    L.fwht_batched_noalloc.argtypes = [vp, vp, vp, C.c_int32, i32, i32, vp]
     L.fwht_threshold.argtypes = [vp, i32, i32, C.POINTER(fwht_thresh_t), vp]
     L.fwht_norms.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     L.fwht_set_schedule.argtypes = [i32, i32, C.c_char_p]
@@ -70,7 +72,7 @@ def lib() -> C.CDLL:
     L.fwht_prime_omega.argtypes = [vp, i32, i32, vp]
     L.fwht_last_error.restype = C.c_char_p
     L.fwht_version.restype = C.c_char_p
-    for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_threshold", "fwht_norms",
+    for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
                  "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_copy",
                  "fwht_trace_enable", "fwht_trace_read", "fwht_fold", "fwht_fold_planted",
                  "fwht_subspace_hits", "fwht_prime_omega"):

@@ -209,8 +209,100 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
 
 }  // namespace fwht
 
-extern "C" int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
-                            int normalize, int prec, void *stream)
+// ---------------------------------------------------------------- no-alloc
+// The allocation-free variant: the work list goes to a fixed device array
+// (tiles first, the segment table after them) instead of a cached plan.
+namespace fwht {
+namespace {
+
+constexpr size_t kNaItemBytes = sizeof(BItem) * FWHT_NOALLOC_MAX_TRANSFORMS;
+constexpr size_t kNaScratchBytes = kNaItemBytes + sizeof(int64_t) * FWHT_NOALLOC_MAX_TRANSFORMS;
+static_assert(sizeof(BItem) == 16, "work-list layout");
+
+// One copy per GPU, for the life of the process.  In host code `scratch`
+// names a host-side stand-in: kernels get the device address found by
+// hipGetSymbolAddress, never the name.
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+constexpr int kNaMaxDevices = 64;
+struct NoAllocDevice {
+    unsigned char *ptr = nullptr;  // device address of this GPU's scratch
+    int grid[3] = {0, 0, 0};       // persistent grid per precision
+};
+std::mutex g_na_mu;
+NoAllocDevice g_na_dev[kNaMaxDevices];
+// host side of the work list (one call at a time, under g_na_mu)
+BItem g_na_items[FWHT_NOALLOC_MAX_TRANSFORMS];
+int64_t g_na_segs[FWHT_NOALLOC_MAX_TRANSFORMS];
+
+// The tiles of build_items (largest transforms first, a size's transforms
+// in the caller's order, 2^(16-m) of them per tile) by a counting sort into
+// the fixed host arrays.
+int32_t build_items_fixed(const int64_t *off, const int32_t *lg, int32_t count)
+{
+    int32_t start[BTB + 2] = {0};
+    for (int32_t t = 0; t < count; ++t) ++start[lg[t]];
+    int32_t pos = 0;
+    for (int m = BTB; m >= 0; --m) {
+        const int32_t c = start[m];
+        start[m] = pos;
+        pos += c;
+    }
+    int32_t next[BTB + 1];
+    for (int m = 0; m <= BTB; ++m) next[m] = start[m];
+    for (int32_t t = 0; t < count; ++t) g_na_segs[next[lg[t]]++] = off[t];
+    int32_t nitems = 0;
+    for (int m = BTB; m >= 0; --m) {
+        const int32_t per = 1 << (BTB - m);
+        for (int32_t k = start[m]; k < next[m]; k += per)
+            g_na_items[nitems++] = BItem{m, k, std::min(per, next[m] - k), 0};
+    }
+    return nitems;
+}
+
+}  // namespace
+
+int batched_noalloc(float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec,
+                    hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(FWHT_E_UNSUPPORTED, "device %d beyond %d", dev, kNaMaxDevices);
+    NoAllocDevice &D = g_na_dev[dev];
+    if (!D.ptr) {  // first call on this device, with it current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+        D.ptr = static_cast<unsigned char *>(p);
+    }
+    if (!D.grid[prec]) {
+        int rc = grid_size(prec, &D.grid[prec]);
+        if (rc) return rc;
+    }
+    const int32_t nitems = build_items_fixed(off, lg, count);
+    BItem *d_items = reinterpret_cast<BItem *>(D.ptr);
+    int64_t *d_segs = reinterpret_cast<int64_t *>(D.ptr + kNaItemBytes);
+    e = hipMemcpyAsync(d_items, g_na_items, sizeof(BItem) * (size_t)nitems, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_segs, g_na_segs, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "work-list copy");
+    BArgs a{};
+    a.data = data;
+    a.items = d_items;
+    a.segs = d_segs;
+    a.nitems = nitems;
+    a.normalize = normalize;
+    e = launch_batched(prec, a, std::min(D.grid[prec], nitems), s);
+    return e == hipSuccess ? FWHT_OK : hip_fail(e, "batched launch");
+}
+
+}  // namespace fwht
+
+namespace {
+
+int check_batched_args(const float *data, const int64_t *offsets, const int32_t *log2n, int32_t count, int prec)
 {
     using namespace fwht;
     if (!data || !offsets || !log2n) return fail(FWHT_E_INVAL, "NULL argument");
@@ -222,5 +314,25 @@ extern "C" int fwht_batched(float *data, const int64_t *offsets, const int32_t *
         if (log2n[t] < 2 || log2n[t] > 16) return fail(FWHT_E_RANGE, "log2n[%d] = %d outside [2, 16]", t, log2n[t]);
         if (offsets[t] < 0 || (offsets[t] & 3)) return fail(FWHT_E_INVAL, "offsets[%d] must be >= 0 and a multiple of 4", t);
     }
-    return batched(data, offsets, log2n, count, normalize, prec, (hipStream_t)stream);
+    return FWHT_OK;
+}
+
+}  // namespace
+
+extern "C" int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
+                            int normalize, int prec, void *stream)
+{
+    const int rc = check_batched_args(data, offsets, log2n, count, prec);
+    if (rc) return rc;
+    return fwht::batched(data, offsets, log2n, count, normalize, prec, (hipStream_t)stream);
+}
+
+extern "C" int fwht_batched_noalloc(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
+                                    int normalize, int prec, void *stream)
+{
+    if (count > FWHT_NOALLOC_MAX_TRANSFORMS)
+        return fwht::fail(FWHT_E_RANGE, "count = %d above the limit of %d", count, FWHT_NOALLOC_MAX_TRANSFORMS);
+    const int rc = check_batched_args(data, offsets, log2n, count, prec);
+    if (rc) return rc;
+    return fwht::batched_noalloc(data, offsets, log2n, count, normalize, prec, (hipStream_t)stream);
 }

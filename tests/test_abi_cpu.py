@@ -181,3 +181,26 @@ def test_batched_validation(L):
     assert call([4, 4], prec=7) == _lib.FWHT_E_INVAL
     assert call([4, 4], data=C.c_void_p(p + 4)) == _lib.FWHT_E_INVAL
     assert call([4, 4], data=None) == _lib.FWHT_E_INVAL
+
+
+def test_batched_noalloc_validation(L):
+    # The allocation-free variant validates like fwht_batched and refuses more
+    # transforms than its fixed work-list array holds.
+    from paper_1607_01039_amd import _lib
+    import numpy as np
+    keep, p = _buf()
+    x = C.c_void_p(p)
+    big = _lib.FWHT_NOALLOC_MAX_TRANSFORMS + 1
+    off = (np.arange(big, dtype=np.int64) * 4)
+    lg = np.full(big, 2, dtype=np.int32)
+    args = (off.ctypes.data_as(C.c_void_p), lg.ctypes.data_as(C.c_void_p))
+    assert L.fwht_batched_noalloc(x, *args, big, 1, 0, None) == _lib.FWHT_E_RANGE
+    assert b"limit" in L.fwht_last_error()
+    lg[1] = 17
+    assert L.fwht_batched_noalloc(x, *args, 2, 1, 0, None) == _lib.FWHT_E_RANGE
+    lg[1] = 2
+    off[1] = 6
+    assert L.fwht_batched_noalloc(x, *args, 2, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_batched_noalloc(x, *args, 0, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_batched_noalloc(x, *args, 1, 1, 5, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_batched_noalloc(None, *args, 1, 1, 0, None) == _lib.FWHT_E_INVAL
