@@ -198,10 +198,13 @@ def main():
     }
 
     if not args.no_extras:
+        out["config_n24"] = bench_n24(F, torch, np, synth)
         out["batched"] = bench_batched(F, torch, np, synth)
         out["autograd"] = bench_autograd(F, torch, np, synth)
         out["subspace"] = bench_subspace(F, torch, np, synth)
         out["prime_omega"] = bench_prime_omega(F, torch, np)
+        log("[bench] streamed int64 n=32 from pinned host memory")
+        out["streamed"] = bench_streamed(F, torch, np, synth, 32)
 
     if not args.no_cpu:
         import oracle
@@ -243,7 +246,7 @@ def main():
 
 
 def _time_replays(torch, fn, reps, flush=None):
-    """Mean device ms of fn() over `reps` calls (each bracketed by events);
+    """Median device ms of fn() over `reps` calls (each bracketed by events);
     `flush` (if given) runs before every call, outside the timed interval."""
     ts = []
     for _ in range(reps):
@@ -293,6 +296,40 @@ def bench_batched(F, torch, np, synth):
     res["speedup_fp16_vs_fp32_warm"] = round(res["fp32"]["ms_warm"] / res["fp16"]["ms_warm"], 3)
     res["speedup_fp16_vs_fp32_cold"] = round(res["fp32"]["ms_cold"] / res["fp16"]["ms_cold"], 3)
     del flushbuf, outs, ref, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_n24(F, torch, np, synth):
+    """int32 transform of 2^24 +-1 signs (seed 1): 64 MiB, which fits the
+    256 MB Infinity Cache, so it is timed warm (input just restored by a
+    device copy) and cold (1 GiB written in between), per call and per pass."""
+    n = 24
+    N = 1 << n
+    src = torch.from_numpy(synth.signs(N, 1)).cuda()
+    buf = torch.empty_like(src)
+    flushbuf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    buf.copy_(src)
+    F.fwht_int_(buf)
+    warm = _time_replays(torch, lambda: F.fwht_int_(buf), 50, flush=lambda: buf.copy_(src))
+    cold = _time_replays(torch, lambda: F.fwht_int_(buf), 20, flush=lambda: (buf.copy_(src), flushbuf.add_(1.0)))
+    F.trace_enable(True)
+    passes = {}
+    for _ in range(20):
+        buf.copy_(src)
+        torch.cuda.synchronize()
+        F.fwht_int_(buf)
+        torch.cuda.synchronize()
+        for name, ms in F.trace_read():
+            passes.setdefault(name, []).append(ms)
+    F.trace_enable(False)
+    per_pass = 2 * N * 4
+    res = {"workload": "int32 WHT n=24 of +-1 signs (seed 1)", "schedule": F.get_schedule("int32", n),
+           "ms_warm": round(warm, 4), "ms_cold": round(cold, 4), "GElem_s_warm": round(N / warm / 1e6, 1),
+           "GElem_s_cold": round(N / cold / 1e6, 1),
+           "passes": [{"pass": k, "ms": round(float(np.mean(v)), 4),
+                       "GBs": round(per_pass / float(np.mean(v)) / 1e6, 1)} for k, v in passes.items()]}
+    del src, buf, flushbuf
     torch.cuda.empty_cache()
     return res
 
