@@ -24,8 +24,9 @@ TABLE = os.path.join(PKG, "tune", "gfx950.txt")
 # Compiled variants (must match csrc/fwht_variants_*.hip).
 CONTIG = {"int32": (12, 13, 14, 15, 16), "float32": (12, 13, 14, 15, 16), "int64": (11, 12, 13, 14)}
 SEGMENT_BITS = {"int32": (5, 6, 7, 8, 9), "float32": (5, 6, 7, 8, 9), "int64": (4, 5, 6, 7)}
-# 2^16-entry strided variants (4-byte types): column bits -> their (only) bit count
-PINNED16 = {7: 9, 8: 8, 9: 7}
+# 256 KiB strided variants held in registers (2^16 4-byte or 2^15 8-byte
+# entries): column bits -> their (only) bit count
+PINNED = {"int32": {7: 9, 8: 8, 9: 7}, "float32": {7: 9, 8: 8, 9: 7}, "int64": {6: 9, 7: 8}}
 MAX_TILE_BYTES = 128 * 1024
 RMAX = 9
 # strided variants from this tile size up (and C16) also exist as twins with
@@ -33,24 +34,36 @@ RMAX = 9
 NT_MIN_TB = {"int32": 13, "float32": 13, "int64": 12}
 
 
+# first passes held in registers (4-byte types), which must be followed by
+# strided passes: 2^16 entries in 1024 threads, 2^15 in 512 threads (two
+# workgroups per CU), each with a non-temporal twin
+WHOLE_FIRST = {16: ("C16", "C16n"), 15: ("C15p", "C15pn")}
+
+
 # row-segment widths compiled for the tile variants of up to 2^15 entries
 TILE_SEGMENT_BITS = {"int32": (5, 6, 7, 8), "float32": (5, 6, 7, 8), "int64": (4, 5, 6, 7)}
 
 
-def strided_variant(dtype: str, r: int, cb: int):
+def strided_variants(dtype: str, r: int, cb: int):
+    """Names of the strided variants that transform r bits over 2^cb columns."""
     esz = 8 if dtype == "int64" else 4
     tb = cb + r
-    if tb == 16 and esz == 4:
-        return f"S16c{cb}" if PINNED16.get(cb) == r else None
+    if (1 << tb) * esz == 256 * 1024:
+        return [f"S{tb}c{cb}"] if PINNED[dtype].get(cb) == r else []
     if cb not in TILE_SEGMENT_BITS[dtype]:
-        return None
+        return []
     if (1 << tb) * esz > MAX_TILE_BYTES:
-        return None
+        return []
     vec = 16 // esz
     nt = (1 << tb) // 32 if tb >= 14 else max(64, (1 << tb) // 16)
     if (1 << tb) // nt < vec:
-        return None
-    return f"S{tb}c{cb}"
+        return []
+    return [f"S{tb}c{cb}"]
+
+
+def _tile_bits(name: str) -> int:
+    """Tile bits of a strided variant name such as "S15c8" or "S15c7p"."""
+    return int(name[1:].split("c")[0])
 
 
 def compositions(s: int, k: int, lo: int = 1, hi: int = RMAX):
@@ -79,22 +92,23 @@ def candidates(dtype: str, n: int, max_cands: int = 1000):
         ns = best_p - 1
         if ns < 1 or s > ns * RMAX or s < ns:
             continue
+        # a 2^15-entry first pass also comes held in registers
+        firsts = (f"C{c}",)
+        if dtype != "int64" and c in WHOLE_FIRST:
+            firsts = WHOLE_FIRST[c] if c == 16 else firsts + WHOLE_FIRST[c]
         for comp in compositions(s, ns, 2 if s >= 2 * ns else 1):
             if max(comp) - min(comp) > 2:
                 continue
-            for cbs in itertools.product(SEGMENT_BITS[dtype], repeat=ns):
-                parts = [strided_variant(dtype, r, cb) for r, cb in zip(comp, cbs)]
-                if None in parts:
-                    continue
-                # cache policy of the first pass and of the strided passes,
-                # chosen independently
-                for nt_first, nt in itertools.product((False, True), repeat=2):
-                    first = f"C{c}n" if nt_first and c == 16 else f"C{c}"
-                    names = [v + "n" if nt and r + cb >= NT_MIN_TB[dtype] else v
-                             for v, r, cb in zip(parts, comp, cbs)]
-                    spec = ",".join([first] + [f"{v}:{r}" for v, r in zip(names, comp)])
-                    if spec not in out:
-                        out.append(spec)
+            strided = itertools.chain.from_iterable(
+                itertools.product(*[strided_variants(dtype, r, cb) for r, cb in zip(comp, cbs)])
+                for cbs in itertools.product(SEGMENT_BITS[dtype], repeat=ns))
+            # cache policy of the first pass and of the strided passes, chosen
+            # independently
+            for parts, first, nt in itertools.product(list(strided), firsts, (False, True)):
+                names = [v + "n" if nt and _tile_bits(v) >= NT_MIN_TB[dtype] else v for v in parts]
+                spec = ",".join([first] + [f"{v}:{r}" for v, r in zip(names, comp)])
+                if spec not in out:
+                    out.append(spec)
     return out[:max_cands]
 
 

@@ -20,6 +20,10 @@ struct Variant {
     int TB, CB, NT;
     bool cols;
     hipError_t (*launch)(void *buf, const PassArgs &a, hipStream_t s);
+    // register-resident tiles (wht_contig16.hpp) transform every bit they
+    // own: a contiguous one only as a first pass followed by strided passes
+    // (it carries no epilogue), a strided one only at its full height
+    bool whole = false;
 };
 
 // One pass of a schedule: variant `v` transforms global bits [lo, lo + r).

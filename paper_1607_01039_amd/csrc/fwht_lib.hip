@@ -86,15 +86,15 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
         int r = want < 0 ? cap : want;
         if (r < 1 || r > cap) { why = "bit count out of range for " + tok; return false; }
         if (r > n - done) r = n - done;
-        // the 2^16-entry contiguous variant transforms exactly its 16 bits and
-        // carries no epilogue, so strided passes must follow it
-        if (v->cols && v->TB == 16 && (r != 16 || done + r >= n)) {
-            why = "C16 covers exactly 16 bits and must be followed by strided passes";
+        // register-resident tiles transform every bit they own: the
+        // contiguous ones carry no epilogue, so strided passes must follow
+        // them, and the strided ones take exactly their full height
+        if (v->whole && v->cols && (r != v->TB || done + r >= n)) {
+            why = "C15p/C16 cover exactly their bits and must be followed by strided passes";
             return false;
         }
-        // the 2^16-entry strided variants transform exactly their 16 - CB bits
-        if (!v->cols && v->TB == 16 && r != cap) {
-            why = "a 2^16-entry strided variant covers exactly its full height";
+        if (v->whole && !v->cols && r != cap) {
+            why = "a register-resident strided variant covers exactly its full height";
             return false;
         }
         out.push_back(Pass{v, done, r});
@@ -307,19 +307,20 @@ template <class S>
 __global__ void __launch_bounds__(256) threshold_kernel(const S *__restrict__ y, uint64_t len, PassArgs a)
 {
     constexpr int VEC = 16 / sizeof(S);
+    const HitTest<S> ht(a);
     const uint64_t stride = (uint64_t)gridDim.x * 256 * VEC;
     for (uint64_t base = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * VEC; base < len; base += stride) {
         if (base + VEC <= len) {
             const uint4 q = *reinterpret_cast<const uint4 *>(y + base);
             const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) emit_hits<S>(Arith<S>::above(qs[e], a), base + e, qs[e], a);
+            for (int e = 0; e < VEC; ++e) emit_hits<S>(ht.above(qs[e]), base + e, qs[e], a);
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 const bool in = base + e < len;
                 const S x = in ? y[base + e] : S(0);
-                emit_hits<S>(in && Arith<S>::above(x, a), base + e, x, a);
+                emit_hits<S>(in && ht.above(x), base + e, x, a);
             }
         }
     }

@@ -16,11 +16,12 @@ std::vector<Variant> variants_f32()
         Variant{"C13", 13, 6, 512, true, &launch_tile<13, 6, 512, true, S, false>},
         Variant{"C14", 14, 6, 512, true, &launch_tile<14, 6, 512, true, S, false>},
         Variant{"C15", 15, 6, 1024, true, &launch_tile<15, 6, 1024, true, S, false>},
-        Variant{"C16", 16, 6, 1024, true, &launch_contig16<S>},
+        Variant{"C15p", 15, 6, 512, true, &launch_contig15p<S>, true},
+        Variant{"C16", 16, 6, 1024, true, &launch_contig16<S>, true},
         // 2^16-entry strided tiles (two-round transposes), full height only
-        Variant{"S16c7", 16, 7, 1024, false, &launch_pinned16<S, 7, 0>},
-        Variant{"S16c8", 16, 8, 1024, false, &launch_pinned16<S, 8, 0>},
-        Variant{"S16c9", 16, 9, 1024, false, &launch_pinned16<S, 9, 0>},
+        Variant{"S16c7", 16, 7, 1024, false, &launch_pinned16<S, 7, 0>, true},
+        Variant{"S16c8", 16, 8, 1024, false, &launch_pinned16<S, 8, 0>, true},
+        Variant{"S16c9", 16, 9, 1024, false, &launch_pinned16<S, 9, 0>, true},
         Variant{"S8c5", 8, 5, 64, false, &launch_tile<8, 5, 64, false, S, false>},
         Variant{"S9c5", 9, 5, 64, false, &launch_tile<9, 5, 64, false, S, false>},
         Variant{"S10c5", 10, 5, 64, false, &launch_tile<10, 5, 64, false, S, false>},
@@ -52,10 +53,11 @@ std::vector<Variant> variants_f32()
         Variant{"S14c8", 14, 8, 512, false, &launch_tile<14, 8, 512, false, S, false>},
         Variant{"S15c8", 15, 8, 1024, false, &launch_tile<15, 8, 1024, false, S, false>},
         // twins with non-temporal loads and stores (the autotuner picks per size)
-        Variant{"C16n", 16, 6, 1024, true, &launch_contig16<S, NT_LOAD | NT_STORE>},
-        Variant{"S16c7n", 16, 7, 1024, false, &launch_pinned16<S, 7, NT_LOAD | NT_STORE>},
-        Variant{"S16c8n", 16, 8, 1024, false, &launch_pinned16<S, 8, NT_LOAD | NT_STORE>},
-        Variant{"S16c9n", 16, 9, 1024, false, &launch_pinned16<S, 9, NT_LOAD | NT_STORE>},
+        Variant{"C15pn", 15, 6, 512, true, &launch_contig15p<S, NT_LOAD | NT_STORE>, true},
+        Variant{"C16n", 16, 6, 1024, true, &launch_contig16<S, NT_LOAD | NT_STORE>, true},
+        Variant{"S16c7n", 16, 7, 1024, false, &launch_pinned16<S, 7, NT_LOAD | NT_STORE>, true},
+        Variant{"S16c8n", 16, 8, 1024, false, &launch_pinned16<S, 8, NT_LOAD | NT_STORE>, true},
+        Variant{"S16c9n", 16, 9, 1024, false, &launch_pinned16<S, 9, NT_LOAD | NT_STORE>, true},
         Variant{"S13c5n", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, NT_LOAD | NT_STORE>},
         Variant{"S14c5n", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, NT_LOAD | NT_STORE>},
         Variant{"S13c6n", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, NT_LOAD | NT_STORE>},

@@ -3,6 +3,7 @@
 // strided pass over tiles of 2^(TB-CB) rows x 2^CB contiguous columns, so it
 // transforms up to TB-CB index bits per pass.
 #include "fwht_internal.hpp"
+#include "wht_contig16.hpp"
 #include "wht_tile.hpp"
 
 namespace fwht {
@@ -15,6 +16,12 @@ std::vector<Variant> variants_u64()
         Variant{"C12", 12, 5, 256, true, &launch_tile<12, 5, 256, true, S, false>},
         Variant{"C13", 13, 5, 512, true, &launch_tile<13, 5, 512, true, S, false>},
         Variant{"C14", 14, 5, 512, true, &launch_tile<14, 5, 512, true, S, false>},
+        // 2^15-entry (256 KiB) strided tiles held in registers with two-round
+        // transposes (wht_contig16.hpp), full height only
+        Variant{"S15c6", 15, 6, 1024, false, &launch_pinned16<S, 6, 0>, true},
+        Variant{"S15c7", 15, 7, 1024, false, &launch_pinned16<S, 7, 0>, true},
+        Variant{"S15c6n", 15, 6, 1024, false, &launch_pinned16<S, 6, NT_LOAD | NT_STORE>, true},
+        Variant{"S15c7n", 15, 7, 1024, false, &launch_pinned16<S, 7, NT_LOAD | NT_STORE>, true},
         Variant{"S7c4", 7, 4, 64, false, &launch_tile<7, 4, 64, false, S, false>},
         Variant{"S8c4", 8, 4, 64, false, &launch_tile<8, 4, 64, false, S, false>},
         Variant{"S9c4", 9, 4, 64, false, &launch_tile<9, 4, 64, false, S, false>},

@@ -1,10 +1,15 @@
-// wht_contig16.hpp -- passes over tiles of 2^16 4-byte entries (256 KiB),
-// twice what LDS holds in one piece.
+// wht_contig16.hpp -- passes over tiles of 256 KiB (2^16 4-byte or 2^15
+// 8-byte entries), twice what LDS holds in one piece.
 //
-// The tile lives in registers (1024 threads x 64 entries) and the top tile
-// bit is a register bit in every layout ("pinned"): each transpose through LDS
-// moves one half of the tile at a time (2^15 entries + padding), the half
-// given by the pinned bit.
+// The tile lives in registers (1024 threads x 64 or 32 entries) and the top
+// tile bit is a register bit in every layout ("pinned"): each transpose
+// through LDS moves one half of the tile at a time (128 KiB + padding), the
+// half given by the pinned bit.  The descriptions below are for 4-byte
+// entries; 8-byte tiles have one bit less everywhere (strided "S15c6",
+// "S15c7": 512-byte and 1 KiB row segments of 2^9 and 2^8 rows), and their
+// layouts, five register bits each, need one transpose more for the same
+// row bits (a CPU model of the 64 banks finds the one-word-per-32 padding
+// free of conflicts for both strided 8-byte tiles).
 //   * contiguous (CB = 0, "C16"): 2^16 consecutive entries, all 16 bits
 //     transformed; layouts L0 {0, 1, 12 .. 15} (16-byte loads), L1 {2 .. 6, 15},
 //     L2 {7 .. 11, 15}.
@@ -22,10 +27,15 @@
 
 namespace fwht {
 
-template <class S, int CB, bool TH, int NTM>
+template <class S, int CB, bool TH, int NTM, int TBX = 0, int NTX = 1024>
 struct Pinned16Kernel {
-    static_assert(sizeof(S) == 4, "2^16 entries of 4 bytes fill half the register file");
-    static constexpr int TB = 16, NT = 1024, E = (1 << TB) / NT, K = 6, VEC = 4, VB = 2;
+    static_assert(sizeof(S) == 4 || sizeof(S) == 8, "4- or 8-byte entries");
+    // 256 KiB tiles: 2^16 entries of 4 bytes (64 per thread) or 2^15 of 8
+    // bytes (32 per thread), half the register file either way; TBX / NTX
+    // give other tile sizes and thread counts (C15p: 2^15 4-byte entries in
+    // 512 threads, two workgroups per CU)
+    static constexpr int TB = TBX ? TBX : sizeof(S) == 4 ? 16 : 15, NT = NTX, E = (1 << TB) / NT, K = clog2(E);
+    static constexpr int VEC = 16 / (int)sizeof(S), VB = clog2(VEC);
     static constexpr bool COLS = CB == 0;
     static constexpr int R = TB - CB;  // transformed bits
     static constexpr LayoutList LS = make_pinned_layouts(TB, K, VB, CB);
@@ -33,8 +43,8 @@ struct Pinned16Kernel {
     static constexpr uint32_t FULL = lowmask(TB);
     static constexpr uint32_t HALF = lowmask(TB - 1);
     static constexpr int LDS_ELEMS = (1 << (TB - 1)) + (1 << (TB - 1)) / 32;
-    static_assert(COLS ? LS.n == 3 : LS.n == 2, "layout count");
-    static_assert(lanes_contiguous(LS.m[LAST], 6), "last layout stores whole 256-byte runs");
+    static_assert(LS.n >= 2 && LS.n <= 4, "layout count");
+    static_assert(lanes_contiguous(LS.m[LAST], 6), "last layout stores whole runs of 64 entries");
     static_assert(CB == 0 || CB >= VB + 5, "a wave's vector loads cover whole 512-byte row segments");
 
     template <int P>
@@ -88,27 +98,25 @@ struct Pinned16Kernel {
     }
 
     // Threshold epilogue around the final stores (as in the 2^15-entry tile
-    // pass): a 64-bit per-thread hit mask before the stores; after them, only
-    // in a wave with a hit, a uniform loop re-reads each hit from the entry
-    // this thread has just written and appends it.
-    __device__ static __forceinline__ uint64_t hit_mask(const S (&v)[E], const PassArgs &a)
+    // pass): whether any element of this thread is a hit before the stores;
+    // after them, only in a wave with a hit, a uniform loop re-reads every
+    // entry this thread has just written, tests it again and appends the hits.
+    __device__ static __forceinline__ bool any_hit(const S (&v)[E], const PassArgs &a)
     {
-        uint64_t hm = 0;
-        static_for<0, E>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            hm |= (uint64_t)Arith<S>::above(v[j], a) << j;
-        });
-        return hm;
+        const HitTest<S> ht(a);
+        bool any = false;
+        static_for<0, E>([&](auto J) { any |= ht.above(v[decltype(J)::value]); });
+        return any;
     }
-    __device__ static __forceinline__ void emit(const S *buf, uint64_t hm, uint64_t lo, const PassArgs &a)
+    __device__ static __forceinline__ void emit(const S *buf, bool any, uint64_t lo, const PassArgs &a)
     {
-        if (__ballot(hm != 0) == 0) return;
+        if (__ballot(any) == 0) return;
+        const HitTest<S> ht(a);
 #pragma unroll 1
         for (int j = 0; j < E; ++j) {
-            const bool hit = (hm >> j) & 1u;
             const uint64_t off = lo + goff(pdep_rt<LS.m[LAST]>((uint32_t)j), a.b);
-            const S val = hit ? buf[off] : S(0);
-            emit_hits<S>(hit, off, val, a);
+            const S val = any ? buf[off] : S(0);
+            emit_hits<S>(any && ht.above(val), off, val, a);
         }
     }
 
@@ -132,13 +140,12 @@ struct Pinned16Kernel {
             });
         }
         reg_stages<S, LS.m[0], LS.fresh[0], E>(v, FULL);
-        transpose<0, 1>(lds, v, t);
-        reg_stages<S, LS.m[1], LS.fresh[1], E>(v, FULL);
-        if constexpr (LS.n == 3) {
-            __syncthreads();
-            transpose<1, 2>(lds, v, t);
-            reg_stages<S, LS.m[2], LS.fresh[2], E>(v, FULL);
-        }
+        static_for<1, LS.n>([&](auto PP) {
+            constexpr int P = decltype(PP)::value;
+            if constexpr (P > 1) __syncthreads();  // the previous transpose's reads are done
+            transpose<P - 1, P>(lds, v, t);
+            reg_stages<S, LS.m[P], LS.fresh[P], E>(v, FULL);
+        });
         if constexpr (std::is_same<S, float>::value) {
             if (a.do_scale) {
 #pragma unroll
@@ -155,13 +162,13 @@ struct Pinned16Kernel {
         static_assert(Split<LAST>::LANE == lowmask(6), "lanes on tile bits 0 .. 5");
         const uint64_t wo = base + goff(pdep_rt<Split<LAST>::WAVE>(swave), a.b);
         S *ub = dst + wo;
-        uint64_t hm = 0;
-        if constexpr (TH) hm = hit_mask(v, a);
+        bool any = false;
+        if constexpr (TH) any = any_hit(v, a);
         static_for<0, E>([&](auto J) {
             constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, LS.m[LAST]);
             gstore1<(NTM & NT_STORE) != 0>(ub + goff(jp, a.b) + slane, v[decltype(J)::value]);
         });
-        if constexpr (TH) emit(dst, hm, wo + slane, a);
+        if constexpr (TH) emit(dst, any, wo + slane, a);
         __syncthreads();  // the next tile reuses the LDS buffer
     }
 
@@ -171,7 +178,12 @@ struct Pinned16Kernel {
         S *out = a.dst ? static_cast<S *>(a.dst) : buf;
         if (a.zero_first && blockIdx.x == 0 && threadIdx.x == 0) *a.zero_first = 0ull;
         const uint32_t cbl = (uint32_t)__builtin_ctzll(a.colblocks);  // colblocks = 2^cbl
-        for (uint64_t tl = blockIdx.x; tl < a.ntiles; tl += gridDim.x) {
+        // Contiguous tiles in XCD-major order: workgroup w runs on XCD w mod 8,
+        // and the workgroups of one XCD take one contiguous eighth of the
+        // tiles (a contiguous in-place pass measured 3% faster this way).
+        const bool xcd = COLS && (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
+        for (uint64_t w = blockIdx.x; w < a.ntiles; w += gridDim.x) {
+            const uint64_t tl = xcd ? ((w & 7) * (a.ntiles >> 3) + (w >> 3)) : w;
             // opaque copies per tile: the offsets derived from them are
             // recomputed for each tile instead of being hoisted and kept live
             uint32_t t = threadIdx.x;
@@ -185,30 +197,31 @@ struct Pinned16Kernel {
     }
 };
 
-template <class S, int CB, bool TH, int NTM>
-__global__ void __launch_bounds__(1024, 1) wht_pinned16_kernel(S *__restrict__ buf, PassArgs a)
+template <class S, int CB, bool TH, int NTM, int TBX = 0, int NTX = 1024>
+__global__ void __launch_bounds__(NTX, 1024 / NTX) wht_pinned16_kernel(S *__restrict__ buf, PassArgs a)
 {
-    Pinned16Kernel<S, CB, TH, NTM>::run(buf, a);
+    Pinned16Kernel<S, CB, TH, NTM, TBX, NTX>::run(buf, a);
 }
 
 // Host launchers.  Every tile is full: the planner schedules these variants
 // only over their full height, and the contiguous one only as the first pass
 // of a transform of at least 2^17 entries, with no epilogue.
-template <class S, int CB, int NTM>
+template <class S, int CB, int NTM, int TBX = 0, int NTX = 1024>
 hipError_t launch_pinned16(void *buf, const PassArgs &a, hipStream_t s)
 {
-    constexpr int R = 16 - CB;
+    constexpr int TB = Pinned16Kernel<S, CB, false, NTM, TBX, NTX>::TB;
+    constexpr int R = TB - CB;
     if (a.act != (lowmask(R) << CB)) return hipErrorInvalidValue;
-    if (CB == 0 && ((a.total & lowmask(16)) || a.thresh)) return hipErrorInvalidValue;
+    if (CB == 0 && ((a.total & lowmask(TB)) || a.thresh)) return hipErrorInvalidValue;
     if (CB > 0 && (((a.total >> a.b) & lowmask(R)) || a.b < (uint32_t)CB)) return hipErrorInvalidValue;
-    const uint64_t maxgrid = (1ull << 31) / 1024;  // work-items counted in 32 bits; grid-stride loop
+    const uint64_t maxgrid = (1ull << 31) / NTX;  // work-items counted in 32 bits; grid-stride loop
     const uint64_t grid = a.ntiles < maxgrid ? a.ntiles : maxgrid;
     if (a.thresh)
-        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, true, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf,
-                           a);
+        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, true, NTM, TBX, NTX>), dim3((uint32_t)grid), dim3(NTX), 0, s,
+                           (S *)buf, a);
     else
-        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, false, NTM>), dim3((uint32_t)grid), dim3(1024), 0, s, (S *)buf,
-                           a);
+        hipLaunchKernelGGL((wht_pinned16_kernel<S, CB, false, NTM, TBX, NTX>), dim3((uint32_t)grid), dim3(NTX), 0, s,
+                           (S *)buf, a);
     return hipGetLastError();
 }
 
@@ -216,6 +229,17 @@ template <class S, int NTM = 0>
 hipError_t launch_contig16(void *buf, const PassArgs &a, hipStream_t s)
 {
     return launch_pinned16<S, 0, NTM>(buf, a, s);
+}
+
+// C15p: the contiguous pass over 2^15 4-byte entries (128 KiB) in 512
+// threads x 64 registers with half-tile transposes (66 KiB of LDS), so that
+// two workgroups share a CU and one's loads and stores overlap the other's
+// LDS phases.  First pass only, over exactly 15 bits, no epilogue.
+template <class S, int NTM = 0>
+hipError_t launch_contig15p(void *buf, const PassArgs &a, hipStream_t s)
+{
+    static_assert(sizeof(S) == 4, "4-byte entries");
+    return launch_pinned16<S, 0, NTM, 15, 512>(buf, a, s);
 }
 
 }  // namespace fwht

@@ -182,29 +182,34 @@ struct PassArgs {
     unsigned long long *zero_first;
 };
 
-template <class S> struct Arith;
-template <> struct Arith<uint32_t> {
-    // |v| <= 2^31 fits 32 bits, so the comparison is done in 32 bits against
-    // T clamped to [0, 2^32 - 1] (T >= 2^31 then matches nothing; T < 0
-    // matches everything).
-    __device__ static bool above(uint32_t v, const PassArgs &a)
+// The threshold test |W_k| > T of one entry, set up once per launch.  For
+// integers it is one add and one unsigned compare: with 0 <= T < 2^(w-1),
+// |v| > T exactly when v lies outside [-T, T], i.e. when (v + T) mod 2^w
+// >= 2T + 1 (v = -2^(w-1), whose magnitude is 2^(w-1), included); T < 0
+// makes the bound 0 (every entry), and for int32 a T >= 2^31 matches nothing
+// (no int32 magnitude exceeds 2^31).
+template <class S> struct HitTest;
+template <> struct HitTest<uint32_t> {
+    uint32_t add, lim;
+    bool none;
+    __device__ explicit HitTest(const PassArgs &a)
+        : add(a.T < 0 ? 0u : (uint32_t)a.T), lim(a.T < 0 ? 0u : 2u * (uint32_t)a.T + 1u), none(a.T >= (1ll << 31))
     {
-        const int32_t s = (int32_t)v;
-        const uint32_t mag = s < 0 ? 0u - v : v;
-        const uint32_t t32 = a.T < 0 ? 0u : a.T > 0xffffffffll ? 0xffffffffu : (uint32_t)a.T;
-        return a.T < 0 || mag > t32;
     }
+    __device__ bool above(uint32_t v) const { return !none && v + add >= lim; }
 };
-template <> struct Arith<uint64_t> {
-    __device__ static bool above(uint64_t v, const PassArgs &a)
+template <> struct HitTest<uint64_t> {
+    uint64_t add, lim;
+    __device__ explicit HitTest(const PassArgs &a)
+        : add(a.T < 0 ? 0ull : (uint64_t)a.T), lim(a.T < 0 ? 0ull : 2ull * (uint64_t)a.T + 1ull)
     {
-        int64_t s = (int64_t)v;
-        uint64_t mag = s < 0 ? 0ull - v : v;
-        return a.T < 0 || mag > (uint64_t)a.T;
     }
+    __device__ bool above(uint64_t v) const { return v + add >= lim; }
 };
-template <> struct Arith<float> {
-    __device__ static bool above(float v, const PassArgs &a) { return fabsf(v) > a.Tf; }
+template <> struct HitTest<float> {
+    float t;
+    __device__ explicit HitTest(const PassArgs &a) : t(a.Tf) {}
+    __device__ bool above(float v) const { return fabsf(v) > t; }
 };
 
 // Wave-aggregated append of one (index, value) hit per lane with `hit` set.
@@ -378,37 +383,39 @@ struct TileKernel {
 
     // Threshold epilogue, in two parts around the final stores from layout M
     // (element j goes to global entry wb + lb/sizeof(S) + goff(pdep(j, M))).
-    // Before the stores: bit j of the mask is set when element j is a hit
-    // (one compare per element).  After them, and only in a wave where some
-    // lane has a hit (rare for thresholds in the noise tail): a uniform loop
-    // over the elements re-reads each hit from the entry this thread has just
-    // written and appends it, so no register array stays live for it.
+    // Before the stores: whether any element of this thread is a hit (one add
+    // and one compare per element, OR-ed into a lane flag).  After them, and
+    // only in a wave where some lane has a hit (rare for thresholds in the
+    // noise tail): a uniform loop over the elements re-reads each entry this
+    // thread has just written, tests it again and appends the hits, so no
+    // register array stays live for it.
     template <uint32_t M, bool FULLT>
-    __device__ static __forceinline__ uint32_t tile_hit_mask(const S (&v)[E], uint64_t wb, uint32_t lb,
-                                                             const PassArgs &a)
+    __device__ static __forceinline__ bool tile_any_hit(const S (&v)[E], uint64_t wb, uint32_t lb,
+                                                        const PassArgs &a)
     {
-        static_assert(E <= 32, "hit mask holds 32 elements");
+        const HitTest<S> ht(a);
         const uint64_t lo = wb + lb / sizeof(S);
-        uint32_t hm = 0;
+        bool any = false;
         static_for<0, E>([&](auto J) {
             constexpr int j = decltype(J)::value;
             const bool in = FULLT || lo + goff(cpdep((uint32_t)j, M), a.b) < a.total;
-            hm |= (uint32_t)(in && Arith<S>::above(v[j], a)) << j;
+            any |= in && ht.above(v[j]);
         });
-        return hm;
+        return any;
     }
-    template <uint32_t M>
-    __device__ static __forceinline__ void emit_tile_hits(const S *buf, uint32_t hm, uint64_t wb, uint32_t lb,
+    template <uint32_t M, bool FULLT>
+    __device__ static __forceinline__ void emit_tile_hits(const S *buf, bool any, uint64_t wb, uint32_t lb,
                                                           const PassArgs &a)
     {
-        if (__ballot(hm != 0) == 0) return;
+        if (__ballot(any) == 0) return;
+        const HitTest<S> ht(a);
         const uint64_t lo = wb + lb / sizeof(S);
 #pragma unroll 1
         for (int j = 0; j < E; ++j) {
-            const bool hit = (hm >> j) & 1u;
             const uint64_t off = lo + goff(pdep_rt<M>((uint32_t)j), a.b);
-            const S val = hit ? buf[off] : S(0);
-            emit_hits<S>(hit, off, val, a);
+            const bool in = any && (FULLT || off < a.total);
+            const S val = in ? buf[off] : S(0);
+            emit_hits<S>(in && ht.above(val), off, val, a);
         }
     }
 
@@ -450,8 +457,8 @@ struct TileKernel {
         constexpr uint32_t M0 = LS.m[0];
         const uint32_t lb = lane_bytes<M0>(lane, a.b);
         const uint64_t wb = base + wave_off<M0>(wave, a.b);
-        uint32_t hm = 0;
-        if constexpr (TH) hm = tile_hit_mask<M0, FULLT>(v, wb, lb, a);
+        bool any = false;
+        if constexpr (TH) any = tile_any_hit<M0, FULLT>(v, wb, lb, a);
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
@@ -471,7 +478,7 @@ struct TileKernel {
                     if (off + e < a.total) buf[off + e] = v[jt * VEC + e];
             }
         });
-        if constexpr (TH) emit_tile_hits<M0>(buf, hm, wb, lb, a);
+        if constexpr (TH) emit_tile_hits<M0, FULLT>(buf, any, wb, lb, a);
     }
 
     template <int P, bool FULLT>
@@ -481,8 +488,8 @@ struct TileKernel {
         constexpr uint32_t M = LS.m[P];
         const uint32_t lb = lane_bytes<M>(lane, a.b);
         const uint64_t wb = base + wave_off<M>(wave, a.b);
-        uint32_t hm = 0;
-        if constexpr (TH) hm = tile_hit_mask<M, FULLT>(v, wb, lb, a);
+        bool any = false;
+        if constexpr (TH) any = tile_any_hit<M, FULLT>(v, wb, lb, a);
         static_for<0, E>([&](auto J) {
             constexpr int j = decltype(J)::value;
             constexpr uint32_t jp = cpdep((uint32_t)j, M);
@@ -494,7 +501,7 @@ struct TileKernel {
                 if (off < a.total) buf[off] = v[j];
             }
         });
-        if constexpr (TH) emit_tile_hits<M>(buf, hm, wb, lb, a);
+        if constexpr (TH) emit_tile_hits<M, FULLT>(buf, any, wb, lb, a);
     }
 
     template <bool FULLT>

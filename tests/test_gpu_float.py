@@ -80,13 +80,16 @@ def _float_variant_cases():
         return [("unbuilt", 0, "")]
     cases = []
     for v in vs:
-        base = v.rstrip("n")  # "n": twin with non-temporal loads and stores
-        if base == "C16":  # only as a first pass over exactly 16 bits
-            cases.append((v, 20, f"{v},S12c8:4"))
-        elif v.startswith("C"):
-            cases.append((v, int(base[1:]), v))
+        base = v[:-1] if v.endswith("n") else v  # "n": twin with non-temporal loads and stores
+        held = base.endswith("p")  # "p": held in registers, two workgroups per CU
+        core = base[:-1] if held else base
+        if core.startswith("C"):
+            if core == "C16" or held:  # only as a first pass over all its bits
+                cases.append((v, int(core[1:]) + 4, f"{v},S12c8:4"))
+            else:
+                cases.append((v, int(core[1:]), v))
         else:
-            tb, cb = (int(x) for x in base[1:].split("c"))
+            tb, cb = (int(x) for x in core[1:].split("c"))
             cases.append((v, 12 + tb - cb, f"C12,{v}:{tb - cb}"))
     return cases
 

@@ -75,19 +75,23 @@ def _variant_cases(dtype):
     import paper_1607_01039_amd as F
     cases = []
     for v in F.list_variants(dtype):
-        base = v.rstrip("n")  # "n": twin with non-temporal loads and stores
-        if base == "C16":  # only as a first pass over exactly 16 bits
-            cases.append((v, 20, f"{v},S12c8:4"))
-            cases.append((v, 17, f"{v},S9c8:1"))
-        elif v.startswith("C"):
-            tb = int(base[1:])
-            cases.append((v, tb, v))
-            cases.append((v, tb - 3, v))
+        base = v[:-1] if v.endswith("n") else v  # "n": twin with non-temporal loads and stores
+        held = base.endswith("p")  # "p": held in registers, two workgroups per CU
+        core = base[:-1] if held else base
+        if core.startswith("C"):
+            tb = int(core[1:])
+            if core == "C16" or held:  # only as a first pass over all its bits
+                cases.append((v, tb + 4, f"{v},S12c8:4"))
+                cases.append((v, tb + 1, f"{v},S9c8:1"))
+            else:
+                cases.append((v, tb, v))
+                cases.append((v, tb - 3, v))
         else:
-            tb, cb = (int(x) for x in base[1:].split("c"))
+            tb, cb = (int(x) for x in core[1:].split("c"))
             R = tb - cb
             cases.append((v, 12 + R, f"C12,{v}:{R}"))
-            if R > 1 and tb < 16:  # 2^16-entry strided tiles: full height only
+            whole = held or (1 << tb) * (8 if dtype == "int64" else 4) == 256 * 1024
+            if R > 1 and not whole:  # register-resident strided tiles: full height only
                 cases.append((v, 12 + R - 1, f"C12,{v}:{R - 1}"))
     return cases
 
