@@ -135,6 +135,22 @@ int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int3
 int fwht_batched_noalloc(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
                          int normalize, int prec, void *stream);
 
+/* Tile groups of the batched transform for precision `prec`: which tile
+ * size takes which transform sizes, e.g. "16:16,15:2-15" (transforms of
+ * 2^16 entries in 2^16-entry tiles of 1024 threads, all smaller ones in
+ * 2^15-entry tiles of 512 threads, two workgroups per CU); a group is
+ * "tb:lo-hi" or "tb:m", tb in {14, 15, 16} (only 16 for the matrix-core
+ * precisions), every size 2^2 .. 2^16 in exactly one group, at most three
+ * groups.  Each group is one persistent launch of the request's graph.
+ * spec = NULL restores the default (the tuned table's "batched" line, else
+ * "16:2-16").  Used by the autotuner.  Results are the same transform; FP32
+ * rounding differs between tile sizes.  Returns FWHT_E_INVAL for a bad spec. */
+int fwht_set_batched_tiles(int prec, const char *spec);
+
+/* The tile groups in use for `prec`, written to buf (NUL-terminated);
+ * FWHT_E_CAPACITY if len is too small. */
+int fwht_get_batched_tiles(int prec, char *buf, int len);
+
 /* Stand-alone threshold pass over 2^n already-transformed device entries of
  * dtype `dtype` (I32/I64 compare |W_k| > th->T exactly in 64 bits; F32
  * compares |W_k| > th->Tf).  *th->count is zeroed by the call and receives

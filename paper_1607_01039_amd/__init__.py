@@ -29,7 +29,8 @@ PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
               "bf16": _lib.FWHT_PREC_BF16_MFMA}
 
 __all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "fwht_batched_noalloc_", "threshold", "fwht", "FWHTFunction",
-           "norms", "set_schedule", "get_schedule", "trace_enable", "trace_read", "copy_",
+           "norms", "set_schedule", "get_schedule", "set_batched_tiles", "get_batched_tiles", "trace_enable",
+           "trace_read", "copy_",
            "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "subspace_scan", "prime_omega",
            "FWHTError", "PRECISIONS"]
 
@@ -371,6 +372,18 @@ def get_schedule(dtype: str, n: int) -> str:
     dt = {"int32": _lib.FWHT_I32, "int64": _lib.FWHT_I64, "float32": _lib.FWHT_F32}[dtype]
     buf = C.create_string_buffer(256)
     _lib.check(_lib.lib().fwht_get_schedule(dt, n, buf, 256))
+    return buf.value.decode()
+
+
+def set_batched_tiles(precision: str, spec):
+    """Tile groups of the batched transform, e.g. "16:16,15:2-15"; None
+    restores the tuned default."""
+    _lib.check(_lib.lib().fwht_set_batched_tiles(PRECISIONS[precision], spec.encode() if spec else None))
+
+
+def get_batched_tiles(precision: str = "fp32") -> str:
+    buf = C.create_string_buffer(256)
+    _lib.check(_lib.lib().fwht_get_batched_tiles(PRECISIONS[precision], buf, 256))
     return buf.value.decode()
 
 

@@ -5,8 +5,11 @@ passes: a contiguous pass of c bits followed by strided passes whose bit
 counts and row-segment widths (2^cb entries) vary, each strided pass using the
 variant whose tile height equals its bit count.  The fastest schedule per
 (dtype, n) is written to tune/gfx950.txt, which libfwht.so reads at start-up.
+With --batched it times the tile groupings of the batched FP32 transform
+instead and writes the fastest as the table's "batched fp32" line.
 
     python -m paper_1607_01039_amd.autotune --dtype int32 --n 16-30
+    python -m paper_1607_01039_amd.autotune --batched
 """
 from __future__ import annotations
 
@@ -169,6 +172,49 @@ def tune(dtype: str, ns, min_total_bits: int = 0, log=print):
     return results
 
 
+# Tile groupings of the batched FP32 transform (see fwht_set_batched_tiles).
+BATCHED_TILES = ["16:2-16", "16:16,15:2-15", "16:16,15:15,14:2-14", "16:15-16,14:2-14", "16:16,15:14-15,14:2-13"]
+
+
+def tune_batched(log=print, reps=30):
+    """Time every tile grouping of the batched FP32 transform on 4096
+    transforms of sizes 2^8..2^16 (N(0,1), seed 4), as the mean of the warm
+    median (input just transformed) and the cold median (1 GiB written in
+    between), and return the fastest as (spec, ms)."""
+    import torch
+
+    import paper_1607_01039_amd as F
+    import synth
+    lg, off, tot = synth.ragged(4096, 8, 16, 4)
+    x = torch.from_numpy(synth.normal(tot, 4)).cuda()
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    best = None
+    for spec in BATCHED_TILES:
+        F.set_batched_tiles("fp32", spec)
+        F.fwht_batched_(x, off, lg)
+        torch.cuda.synchronize()
+        med = []
+        for cold in (False, True):
+            ts = []
+            for _ in range(reps):
+                if cold:
+                    flush.add_(1.0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                F.fwht_batched_(x, off, lg)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            med.append(float(np.median(ts)))
+        ms = (med[0] + med[1]) / 2
+        log(f"[tune] batched fp32 {spec}: warm {med[0]:.4f} ms, cold {med[1]:.4f} ms")
+        if best is None or ms < best[1]:
+            best = (spec, ms)
+    F.set_batched_tiles("fp32", None)
+    log(f"[tune] batched fp32 best {best[0]} {best[1]:.4f} ms")
+    return best
+
+
 def write_table(path: str, updates: dict):
     """Merge {(dtype, n): (spec, ms)} into the table file."""
     rows = {}
@@ -176,12 +222,13 @@ def write_table(path: str, updates: dict):
         for line in open(path):
             line = line.split("#")[0].split()
             if len(line) >= 3:
-                rows[(line[0], int(line[1]))] = (line[2], float(line[3]) if len(line) > 3 else float("nan"))
+                key = (line[0], line[1] if line[0] == "batched" else int(line[1]))
+                rows[key] = (line[2], float(line[3]) if len(line) > 3 else float("nan"))
     rows.update(updates)
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         f.write("# dtype n schedule ms  -- written by paper_1607_01039_amd/autotune.py on MI355X (gfx950)\n")
-        for (dt, n) in sorted(rows, key=lambda k: (k[0], k[1])):
+        for (dt, n) in sorted(rows, key=lambda k: (k[0], str(k[1]).zfill(8))):
             spec, ms = rows[(dt, n)]
             f.write(f"{dt} {n} {spec} {ms:.4f}\n")
 
@@ -204,7 +251,12 @@ def main():
     ap.add_argument("--float-total-bits", type=int, default=28,
                     help="float32: batch so that batch * 2^n = 2^this (the transform size stays 2^n)")
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--batched", action="store_true", help="tune the tile groups of the batched FP32 transform")
     args = ap.parse_args()
+    if args.batched:
+        write_table(args.out, {("batched", "fp32"): tune_batched(log=lambda m: print(m, flush=True))})
+        print(f"wrote {args.out}", flush=True)
+        return
     res = tune(args.dtype, parse_range(args.n), args.float_total_bits,
                log=lambda m: print(m, flush=True))
     write_table(args.out, {(args.dtype, n): v for n, v in res.items()})

@@ -63,8 +63,17 @@ int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, c
 int zero_count(uint64_t *count, hipStream_t s);
 float float_threshold(double T);
 
-// batched persistent path (fwht_batched.hip, fwht_mfma.hip)
-hipError_t launch_batched(int prec, const BArgs &a, int grid, hipStream_t s);
+// batched persistent path (fwht_batched.hip, fwht_mfma.hip): transforms of
+// 2^lo .. 2^hi entries go to tiles of 2^tb entries
+struct TileGroup {
+    int tb = 16, lo = 2, hi = 16;
+};
+struct TilePlan {
+    int n = 0;
+    TileGroup g[3];
+};
+bool parse_tiles(int prec, const std::string &spec, TilePlan &out, std::string &why);
+const std::string *tuned_batched_tiles(int prec);
 hipError_t launch_batched_mfma(int prec, const BArgs &a, int grid, hipStream_t s);
 hipError_t batched_mfma_occupancy(int prec, int *blocks_per_cu);
 int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec,

@@ -206,3 +206,19 @@ def test_batched_noalloc_validation(L):
     assert L.fwht_batched_noalloc(x, *args, 0, 1, 0, None) == _lib.FWHT_E_INVAL
     assert L.fwht_batched_noalloc(x, *args, 1, 1, 5, None) == _lib.FWHT_E_INVAL
     assert L.fwht_batched_noalloc(None, *args, 1, 1, 0, None) == _lib.FWHT_E_INVAL
+
+
+def test_batched_tile_groups_parsing(L):
+    from paper_1607_01039_amd import _lib
+    buf = C.create_string_buffer(64)
+    for spec in (b"16:2-16", b"16:16,15:2-15", b"16:16,15:15,14:2-14", b"15:2-15,16:16"):
+        assert L.fwht_set_batched_tiles(0, spec) == 0, (spec, L.fwht_last_error())
+        assert L.fwht_get_batched_tiles(0, buf, 64) == 0 and buf.value == spec
+    assert L.fwht_set_batched_tiles(1, b"16:2-16") == 0
+    bad = [(0, b"16:2-15"), (0, b"16:2-16,15:15"), (0, b"17:2-16"), (0, b"13:2-13,16:14-16"), (0, b"15:2-16"),
+           (0, b"16:1-16"), (0, b"16:x"), (1, b"16:16,15:2-15"), (0, b"16:16,15:15,14:3-14,14:2"), (5, b"16:2-16")]
+    for prec, spec in bad:
+        assert L.fwht_set_batched_tiles(prec, spec) == _lib.FWHT_E_INVAL, spec
+    assert L.fwht_set_batched_tiles(0, None) == 0 and L.fwht_set_batched_tiles(1, None) == 0
+    small = C.create_string_buffer(3)
+    assert L.fwht_get_batched_tiles(0, small, 3) == _lib.FWHT_E_CAPACITY

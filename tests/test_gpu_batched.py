@@ -50,6 +50,27 @@ def test_batched_matches_oracle(F, O, count, lo, hi, seed, normalize):
     assert np.all(errs <= (lg + 2) * 2.0 ** -23), (errs.max(), lg[np.argmax(errs)])
 
 
+TILE_GROUPS = ["16:2-16", "16:16,15:2-15", "16:16,15:15,14:2-14", "16:14-16,15:2-13", "16:16,14:2-14,15:15"]
+
+
+@pytest.mark.parametrize("spec", TILE_GROUPS)
+@pytest.mark.parametrize("count,lo,hi,seed", [(4096, 8, 16, 4), (700, 2, 16, 13), (5000, 2, 6, 14)])
+def test_batched_tile_groups(F, O, spec, count, lo, hi, seed):
+    """Every grouping of the sizes over 2^16-, 2^15- and 2^14-entry tiles gives
+    the transform (each group one persistent launch of the graph)."""
+    F.set_batched_tiles("fp32", spec)
+    try:
+        assert F.get_batched_tiles("fp32") == spec
+        lg, off, tot = synth.ragged(count, lo, hi, seed)
+        x = synth.normal(tot, seed + 200)
+        y = run_batched(F, x, off, lg, True, reps=1)
+    finally:
+        F.set_batched_tiles("fp32", None)
+    ref = O.wht_ragged(x, off, lg, True)
+    errs = per_transform_err(y, ref, off, lg)
+    assert np.all(errs <= (lg + 2) * 2.0 ** -23), (errs.max(), lg[np.argmax(errs)])
+
+
 def test_batched_config_4096(F, O):
     """4096 transforms, sizes 2^U{8..16}, x ~ N(0,1) (seed 4): every transform."""
     lg, off, tot = synth.ragged(4096, 8, 16, 4)

@@ -305,7 +305,7 @@ def _tuned_table():
     tab = {}
     for ln in open(path):
         f = ln.split()
-        if f and not ln.startswith("#"):
+        if f and not ln.startswith("#") and f[0] != "batched":
             tab[(f[0], int(f[1]))] = f[2]
     return tab
 
