@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--n", type=int, default=N_BITS)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (FP32 vs MFMA) and autograd measurements")
+    ap.add_argument("--no-streamed", action="store_true",
+                    help="skip the streamed int64 n = 32 extra (32 GiB of pinned host memory)")
     ap.add_argument("--streamed", type=int, default=0, metavar="N",
                     help="instead of the default workload, time the streamed path on an int64 planted "
                          "signal of 2^N entries held in pinned host memory (10 <= N <= 32)")
@@ -203,8 +205,9 @@ def main():
         out["autograd"] = bench_autograd(F, torch, np, synth)
         out["subspace"] = bench_subspace(F, torch, np, synth)
         out["prime_omega"] = bench_prime_omega(F, torch, np)
-        log("[bench] streamed int64 n=32 from pinned host memory")
-        out["streamed"] = bench_streamed(F, torch, np, synth, 32)
+        if not args.no_streamed:
+            log("[bench] streamed int64 n=32 from pinned host memory")
+            out["streamed"] = bench_streamed(F, torch, np, synth, 32)
 
     if not args.no_cpu:
         import oracle
