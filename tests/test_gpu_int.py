@@ -366,18 +366,24 @@ def test_int64_large_in_hbm(F, O, n):
     """int64 up to the in-HBM limit (n = 34: 128 GiB resident), planted peak
     (seed 3, p = 0.48), fused threshold T = ceil(6 * 2^(n/2)): every entry
     against the oracle's Fig. 2 run in place on the host copy of the input,
-    the hit set against the oracle's threshold scan, and the peak in closed
-    form."""
+    the hit set against the oracle's threshold scan, the peak in closed form,
+    and the randomized Kronecker-weight identity (independent of Fig. 2)."""
     import math
     import torch
     N = 1 << n
     T = int(math.ceil(6 * 2 ** (n / 2)))
     print(f"int64 in HBM n={n}: generating", flush=True)
     x, s, err = synth.planted(n, 3, 0.48, dtype=np.int64)
+    # the randomized identity sum_k W_k w_k = sum_i x_i (H w)_i (mod 2^61 - 1)
+    # for Kronecker-product weights, input side taken before Fig. 2 runs in place
+    tw = [int(v) for v in np.random.default_rng(n).integers(0, O.KF_P, size=n, dtype=np.uint64)]
+    kf_in = O.kf_sum(x, n, tw, 1)
     t = _upload(x)
     print("transforming", flush=True)
     hits = F.fwht_int_(t, threshold=T, cap=1 << 12)
     assert int(t[s].item()) == N - 2 * err
+    kf_out = sum(O.kf_sum(t[c0:c0 + CHUNK].cpu().numpy(), n, tw, 0, start=c0) for c0 in range(0, N, CHUNK)) % O.KF_P
+    assert kf_out == kf_in
     print("oracle (Fig. 2, 16 threads)", flush=True)
     O.wht_fig2_inplace(x, 4)
     print("comparing", flush=True)
