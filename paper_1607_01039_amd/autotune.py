@@ -37,10 +37,15 @@ RMAX = 9
 NT_MIN_TB = {"int32": 13, "float32": 13, "int64": 12}
 
 
-# first passes held in registers (4-byte types), which must be followed by
-# strided passes: 2^16 entries in 1024 threads, 2^15 in 512 threads (two
+# first passes held in registers, which must be followed by strided passes:
+# 256 KiB tiles in 1024 threads, 128 KiB tiles in 512 threads (two
 # workgroups per CU), each with a non-temporal twin
-WHOLE_FIRST = {16: ("C16", "C16n"), 15: ("C15p", "C15pn")}
+WHOLE_FIRST = {"int32": {16: ("C16", "C16n"), 15: ("C15p", "C15pn")},
+               "float32": {16: ("C16", "C16n"), 15: ("C15p", "C15pn")},
+               "int64": {14: ("C14p", "C14pn")}}
+# strided variants held in registers by 512 threads, two workgroups per CU
+# (8-byte types): (column bits, row bits) -> name
+HELD = {"int64": {(6, 8): "S14c6p"}}
 
 
 # row-segment widths compiled for the tile variants of up to 2^15 entries
@@ -61,7 +66,10 @@ def strided_variants(dtype: str, r: int, cb: int):
     nt = (1 << tb) // 32 if tb >= 14 else max(64, (1 << tb) // 16)
     if (1 << tb) // nt < vec:
         return []
-    return [f"S{tb}c{cb}"]
+    out = [f"S{tb}c{cb}"]
+    if (cb, r) in HELD.get(dtype, {}):
+        out.append(HELD[dtype][(cb, r)])
+    return out
 
 
 def _tile_bits(name: str) -> int:
@@ -97,8 +105,8 @@ def candidates(dtype: str, n: int, max_cands: int = 1000):
             continue
         # a 2^15-entry first pass also comes held in registers
         firsts = (f"C{c}",)
-        if dtype != "int64" and c in WHOLE_FIRST:
-            firsts = WHOLE_FIRST[c] if c == 16 else firsts + WHOLE_FIRST[c]
+        if c in WHOLE_FIRST[dtype]:
+            firsts = WHOLE_FIRST[dtype][c] if c == 16 else firsts + WHOLE_FIRST[dtype][c]
         for comp in compositions(s, ns, 2 if s >= 2 * ns else 1):
             if max(comp) - min(comp) > 2:
                 continue

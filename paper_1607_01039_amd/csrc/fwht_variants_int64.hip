@@ -22,6 +22,11 @@ std::vector<Variant> variants_u64()
         Variant{"S15c7", 15, 7, 1024, false, &launch_pinned16<S, 7, 0>, true},
         Variant{"S15c6n", 15, 6, 1024, false, &launch_pinned16<S, 6, NT_LOAD | NT_STORE>, true},
         Variant{"S15c7n", 15, 7, 1024, false, &launch_pinned16<S, 7, NT_LOAD | NT_STORE>, true},
+        // 2^14-entry tiles in 512 threads, two workgroups per CU
+        Variant{"C14p", 14, 5, 512, true, &launch_contig15p<S>, true},
+        Variant{"C14pn", 14, 5, 512, true, &launch_contig15p<S, NT_LOAD | NT_STORE>, true},
+        Variant{"S14c6p", 14, 6, 512, false, &launch_strided14p<S, 6>, true},
+        Variant{"S14c6pn", 14, 6, 512, false, &launch_strided14p<S, 6, NT_LOAD | NT_STORE>, true},
         Variant{"S7c4", 7, 4, 64, false, &launch_tile<7, 4, 64, false, S, false>},
         Variant{"S8c4", 8, 4, 64, false, &launch_tile<8, 4, 64, false, S, false>},
         Variant{"S9c4", 9, 4, 64, false, &launch_tile<9, 4, 64, false, S, false>},

@@ -42,7 +42,11 @@ struct Pinned16Kernel {
     static constexpr int LAST = LS.n - 1;
     static constexpr uint32_t FULL = lowmask(TB);
     static constexpr uint32_t HALF = lowmask(TB - 1);
-    static constexpr int LDS_ELEMS = (1 << (TB - 1)) + (1 << (TB - 1)) / 32;
+    // LDS padding, entries per 32: one, except two for the contiguous 8-byte
+    // tile, whose second layout would otherwise read with 2-way bank
+    // conflicts (CPU model of the 64 banks)
+    static constexpr uint32_t PAD = sizeof(S) == 8 && COLS ? 2 : 1;
+    static constexpr int LDS_ELEMS = (1 << (TB - 1)) + PAD * ((1 << (TB - 1)) / 32);
     static_assert(LS.n >= 2 && LS.n <= 4, "layout count");
     static_assert(lanes_contiguous(LS.m[LAST], 6), "last layout stores whole runs of 64 entries");
     static_assert(CB == 0 || CB >= VB + 5, "a wave's vector loads cover whole 512-byte row segments");
@@ -65,24 +69,28 @@ struct Pinned16Kernel {
 
     // Half H of the registers of layout P (those whose pinned bit is H) to
     // LDS, or back; the LDS index drops the pinned bit.
+    // padded LDS index; additive over disjoint bit sets, so the thread part
+    // and the register part are padded separately
+    __device__ static __forceinline__ constexpr uint32_t pad(uint32_t i) { return i + PAD * (i >> 5); }
+
     template <int P, int H>
     __device__ static __forceinline__ void to_lds(S *lds, const S (&v)[E], uint32_t t)
     {
         constexpr uint32_t M = LS.m[P];
-        const uint32_t tb = lds_pad(pdep_rt<FULL & ~M>(t));
+        const uint32_t tb = pad(pdep_rt<FULL & ~M>(t));
         static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
             constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, M) & HALF;
-            lds[tb + jp + (jp >> 5)] = v[decltype(J)::value];
+            lds[tb + pad(jp)] = v[decltype(J)::value];
         });
     }
     template <int P, int H>
     __device__ static __forceinline__ void from_lds(const S *lds, S (&v)[E], uint32_t t)
     {
         constexpr uint32_t M = LS.m[P];
-        const uint32_t tb = lds_pad(pdep_rt<FULL & ~M>(t));
+        const uint32_t tb = pad(pdep_rt<FULL & ~M>(t));
         static_for<H * (E / 2), (H + 1) * (E / 2)>([&](auto J) {
             constexpr uint32_t jp = cpdep((uint32_t)decltype(J)::value, M) & HALF;
-            v[decltype(J)::value] = lds[tb + jp + (jp >> 5)];
+            v[decltype(J)::value] = lds[tb + pad(jp)];
         });
     }
     template <int FROM, int TO>
@@ -231,15 +239,22 @@ hipError_t launch_contig16(void *buf, const PassArgs &a, hipStream_t s)
     return launch_pinned16<S, 0, NTM>(buf, a, s);
 }
 
-// C15p: the contiguous pass over 2^15 4-byte entries (128 KiB) in 512
-// threads x 64 registers with half-tile transposes (66 KiB of LDS), so that
-// two workgroups share a CU and one's loads and stores overlap the other's
-// LDS phases.  First pass only, over exactly 15 bits, no epilogue.
+// 128 KiB tiles held the same way by 512 threads (64 registers of 4-byte or
+// 32 of 8-byte entries) with half-tile transposes through 66-68 KiB of LDS,
+// so that two workgroups share a CU and one's loads and stores overlap the
+// other's LDS phases: "C15p" (2^15 4-byte entries) and "C14p" (2^14 8-byte
+// entries), first passes only, over exactly their bits, no epilogue; and the
+// strided 8-byte "S14c6p" (2^8 rows x 512 B).
 template <class S, int NTM = 0>
 hipError_t launch_contig15p(void *buf, const PassArgs &a, hipStream_t s)
 {
-    static_assert(sizeof(S) == 4, "4-byte entries");
-    return launch_pinned16<S, 0, NTM, 15, 512>(buf, a, s);
+    return launch_pinned16<S, 0, NTM, sizeof(S) == 4 ? 15 : 14, 512>(buf, a, s);
+}
+template <class S, int CB, int NTM = 0>
+hipError_t launch_strided14p(void *buf, const PassArgs &a, hipStream_t s)
+{
+    static_assert(sizeof(S) == 8, "8-byte entries");
+    return launch_pinned16<S, CB, NTM, 14, 512>(buf, a, s);
 }
 
 }  // namespace fwht

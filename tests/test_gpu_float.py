@@ -49,6 +49,20 @@ def test_float_matches_oracle(F, O, n, batch, normalize):
     assert normwise(t.cpu().numpy(), ref) <= tol(n)
 
 
+@pytest.mark.parametrize("n", list(range(13, 29)))
+def test_float_default_schedule(F, O, n):
+    """The tuned default schedule of every size of the table (n = 13..28), one
+    transform per row, two rows up to n = 26, against the FP64 oracle."""
+    batch = 2 if n <= 26 else 1
+    x = synth.normal((batch, 1 << n), 500 + n)
+    print(f"float32 n={n} schedule {F.get_schedule('float32', n)}", flush=True)
+    t = _dev(x)
+    F.fwht_float_(t, normalize=True)
+    y = t.cpu().numpy()
+    del t
+    assert normwise(y, O.wht_batch(x, n, True)) <= tol(n)
+
+
 def test_float_config_autograd_shape(F, O):
     # 256 x 2^20 orthonormal (the autograd workload), sampled rows vs the oracle.
     n, B = 20, 256

@@ -81,8 +81,9 @@ def _variant_cases(dtype):
         if core.startswith("C"):
             tb = int(core[1:])
             if core == "C16" or held:  # only as a first pass over all its bits
-                cases.append((v, tb + 4, f"{v},S12c8:4"))
-                cases.append((v, tb + 1, f"{v},S9c8:1"))
+                s4, s1 = ("S11c7:4", "S8c7:1") if dtype == "int64" else ("S12c8:4", "S9c8:1")
+                cases.append((v, tb + 4, f"{v},{s4}"))
+                cases.append((v, tb + 1, f"{v},{s1}"))
             else:
                 cases.append((v, tb, v))
                 cases.append((v, tb - 3, v))
