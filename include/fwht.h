@@ -60,6 +60,9 @@ typedef enum {
 } fwht_prec;
 
 /* Threshold request (problem statement of the abstract and section 1).
+ * The fused extraction of fwht_int and the stand-alone fwht_threshold both
+ * take this one struct (the bound and the caller's output buffers together)
+ * instead of separate arguments, so both passes share one layout.
  * All pointers are device pointers for device-path calls and host pointers
  * for the synchronous pinned-host path of fwht_int. */
 typedef struct {
@@ -101,14 +104,18 @@ int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream
  * 4 <= n <= 16 (otherwise FWHT_E_UNSUPPORTED). */
 int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void *stream);
 
-/* In-place float WHT of `count` independent transforms of uneven sizes in
- * one persistent launch replayed from a cached HIP graph.
+/* In-place float WHT of `count` independent transforms of uneven sizes
+ * (the orthonormal or unnormalised Eq. 2 of each; batching is this
+ * library's extension, not the paper's) in persistent launches replayed
+ * from a cached HIP graph: one launch per tile group (see
+ * fwht_set_batched_tiles; by default one group, hence one launch).
  *   data    : device FP32 buffer; transform t occupies
  *             data[offsets[t] .. offsets[t] + 2^log2n[t]).
  *   offsets : HOST array [count] of entry offsets (each a multiple of 4).
  *   log2n   : HOST array [count], each in [2, 16] (FWHT_E_RANGE otherwise).
- * The work list is built from the host arrays on the first call with a given
- * (data, count, normalize, prec, contents of offsets/log2n) and cached with
+ * offsets and log2n are host arrays (not device arrays): the work list is
+ * built from them on the host on the first call with a given (data, count,
+ * normalize, prec, tile groups, contents of offsets/log2n) and cached with
  * its graph, together with a copy of both arrays; a later call whose
  * arguments equal a cached request element for element only replays that
  * graph on `stream`.
