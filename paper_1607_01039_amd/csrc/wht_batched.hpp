@@ -147,16 +147,27 @@ struct BatchedKernel {
         constexpr uint32_t M0 = LS.m[0];
         const uint32_t lp = pdep_rt<Split<0>::LANE>(lane);
         const uint32_t wp = pdep_rt<Split<0>::WAVE>(wave);
+        // all loads first, the empty slots zeroed only after every load has
+        // been issued (see the scheduling barrier in item())
+        uint32_t okm = 0;
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = cpdep((uint32_t)(jt << VB), M0);
             bool ok;
             const S *p = addr<MM, Split<0>::LANE>(a, I, jp, wp, lp, ok);
-            v4u q = *reinterpret_cast<const v4u *>(p);
-            if (!ok) q = v4u{0u, 0u, 0u, 0u};
+            const v4u q = *reinterpret_cast<const v4u *>(p);
+            okm |= (uint32_t)ok << jt;
             const S *qs = reinterpret_cast<const S *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<0, E / VEC>([&](auto JT) {
+            constexpr int jt = decltype(JT)::value;
+            if (!((okm >> jt) & 1u)) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = S(0);
+            }
         });
     }
 
@@ -219,6 +230,9 @@ struct BatchedKernel {
         const uint32_t lane = t & 63u;
         const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
         S v[E];
+        // every load is issued before the first use: the counter that tracks
+        // the loads also counts the previous item's stores, so consuming the
+        // first load early would drain those stores before the others issue
         load0<MM>(a, I, v, lane, wave);
         reg_stages<S, LS.m[0], LS.fresh[0], E>(v, act);
         int cur = 0;

@@ -272,16 +272,27 @@ struct BatchedMfmaKernel {
     {
         constexpr uint32_t LM = xl_lane_mask(XL_A);
         const uint32_t lp = lane_part<0>(lane), wp = wave_part<0>(wave);
+        // all loads first, the empty slots zeroed after every load has been
+        // issued (as in the FP32 kernel)
+        uint32_t okm = 0;
         static_for<0, E / VEC>([&](auto JT) {
             constexpr int jt = decltype(JT)::value;
             constexpr uint32_t jp = xl_reg_part(XL_A, (uint32_t)(jt << 2));
             bool ok;
             const float *p = Base::template addr<MM, LM>(a, I, jp, wp, lp, ok);
-            v4u q = *reinterpret_cast<const v4u *>(p);
-            if (!ok) q = v4u{0u, 0u, 0u, 0u};
+            const v4u q = *reinterpret_cast<const v4u *>(p);
+            okm |= (uint32_t)ok << jt;
             const float *qs = reinterpret_cast<const float *>(&q);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        static_for<0, E / VEC>([&](auto JT) {
+            constexpr int jt = decltype(JT)::value;
+            if (!((okm >> jt) & 1u)) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = 0.f;
+            }
         });
     }
 

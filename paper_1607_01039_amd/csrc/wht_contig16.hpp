@@ -147,6 +147,11 @@ struct Pinned16Kernel {
                 for (int e = 0; e < VEC; ++e) v[jt * VEC + e] = qs[e];
             });
         }
+        // Every load of the tile is issued before the first butterfly: the
+        // previous tile's stores are still in flight, and the counter that
+        // tracks loads also counts them, so consuming the first load early
+        // would wait for all of them before the other loads were issued.
+        __builtin_amdgcn_sched_barrier(0);
         reg_stages<S, LS.m[0], LS.fresh[0], E>(v, FULL);
         static_for<1, LS.n>([&](auto PP) {
             constexpr int P = decltype(PP)::value;
@@ -190,7 +195,11 @@ struct Pinned16Kernel {
         // and the workgroups of one XCD take one contiguous eighth of the
         // tiles (a contiguous in-place pass measured 3% faster this way).
         const bool xcd = COLS && (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
-        for (uint64_t w = blockIdx.x; w < a.ntiles; w += gridDim.x) {
+        // scalar trip count (see the tile kernel's loop)
+        const uint64_t first = blockIdx.x;
+        const uint32_t iters = a.ntiles > first ? (uint32_t)((a.ntiles - first - 1) / gridDim.x + 1) : 0u;
+        for (uint32_t k = 0; k < iters; ++k) {
+            const uint64_t w = first + (uint64_t)k * gridDim.x;
             const uint64_t tl = xcd ? ((w & 7) * (a.ntiles >> 3) + (w >> 3)) : w;
             // opaque copies per tile: the offsets derived from them are
             // recomputed for each tile instead of being hoisted and kept live

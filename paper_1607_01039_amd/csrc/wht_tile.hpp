@@ -524,6 +524,9 @@ struct TileKernel {
         const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
         S v[E];
         load_vec<FULLT>(buf, v, lane, wave, base, a);
+        // every load issued before the first butterfly (the previous tile's
+        // stores share the counter that the first use would wait on)
+        __builtin_amdgcn_sched_barrier(0);
         reg_stages<S, LS.m[0], LS.fresh[0], E>(v, a.act);
         // remaining layouts, skipping those that own no transformed bit
         int cur = 0;
@@ -571,7 +574,14 @@ struct TileKernel {
         if (a.zero_first && blockIdx.x == 0 && t == 0) *a.zero_first = 0ull;
         const uint32_t b = COLS ? (uint32_t)CB : a.b;
         const uint32_t cbl = (uint32_t)__builtin_ctzll(a.colblocks);  // colblocks = 2^cbl
-        for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        // Scalar trip count: a 64-bit tile < ntiles test would be a vector
+        // compare against a vector copy of ntiles, which the compiler may
+        // rebuild at the loop latch in registers that the stores just read,
+        // and then waits for every store to finish before the next tile.
+        const uint64_t first = blockIdx.x;
+        const uint32_t iters = a.ntiles > first ? (uint32_t)((a.ntiles - first - 1) / gridDim.x + 1) : 0u;
+        for (uint32_t k = 0; k < iters; ++k) {
+            const uint64_t tile = first + (uint64_t)k * gridDim.x;
             const uint64_t g = tile >> cbl;
             const uint64_t cb = tile & (a.colblocks - 1);
             const uint64_t base = ((g << R) << b) + (cb << CB);
