@@ -258,7 +258,8 @@ int fwht_prime_omega(void *data, int dtype, int n, void *stream);
  * whose traffic calibrates the HBM counters.  Asynchronous. */
 int fwht_copy(void *dst, const void *src, uint64_t bytes, void *stream);
 
-/* Message for the last non-zero return on this thread ("" if none). */
+/* Message for the last non-zero return on this thread ("" if none); read it
+ * right after that return, since a later call may clear it. */
 const char *fwht_last_error(void);
 
 /* Library version string. */
