@@ -266,8 +266,9 @@ def _time_replays(torch, fn, reps, flush=None):
 
 def bench_batched(F, torch, np, synth):
     """4096 orthonormal transforms of sizes 2^U{8..16}, x ~ N(0,1) (seed 4), one
-    persistent launch per call replayed from the cached graph: FP32 VALU path
-    against the f16 / bf16 radix-16 matrix-core paths.  Warm = data left in
+    persistent launch per call from the cached work list: FP32 VALU path
+    against the f16 / bf16 radix-16 matrix-core paths (and, for FP32, the same
+    launch replayed from a captured HIP graph).  Warm = data left in
     the 256 MB Infinity Cache by the previous call; cold = a 1 GiB buffer is
     streamed between calls.  Accuracy here uses the library's FP64 norm
     reductions on the GPU: the normwise distance of each reduced-precision
@@ -281,7 +282,7 @@ def bench_batched(F, torch, np, synth):
     outs = {}
     for prec in ("fp32", "fp16", "bf16"):
         t = x.clone()
-        F.fwht_batched_(t, off, lg, precision=prec)  # builds and caches the graph
+        F.fwht_batched_(t, off, lg, precision=prec)  # builds and caches the work list
         torch.cuda.synchronize()
         outs[prec] = t.clone()
         warm = _time_replays(torch, lambda: F.fwht_batched_(t, off, lg, precision=prec), 30)
@@ -291,6 +292,14 @@ def bench_batched(F, torch, np, synth):
         res[prec] = {"ms_warm": round(warm, 4), "ms_cold": round(cold, 4),
                      "GBs_warm": round(algo_bytes / warm / 1e6, 1), "GBs_cold": round(algo_bytes / cold / 1e6, 1),
                      "parseval_defect_max": float(f"{np.max(np.abs(nr[:, 1] - nr[:, 0]) / nr[:, 0]):.3e}")}
+        if prec == "fp32":
+            F.set_batched_graphs(True)
+            try:
+                F.fwht_batched_(t, off, lg, precision=prec)  # captures the graph
+                res[prec]["graph_replay_ms_warm"] = round(
+                    _time_replays(torch, lambda: F.fwht_batched_(t, off, lg, precision=prec), 30), 4)
+            finally:
+                F.set_batched_graphs(False)
         del t
     ref = outs["fp32"].double()
     for prec in ("fp16", "bf16"):

@@ -106,19 +106,21 @@ int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void 
 
 /* In-place float WHT of `count` independent transforms of uneven sizes
  * (the orthonormal or unnormalised Eq. 2 of each; batching is this
- * library's extension, not the paper's) in persistent launches replayed
- * from a cached HIP graph: one launch per tile group (see
- * fwht_set_batched_tiles; by default one group, hence one launch).
+ * library's extension, not the paper's) in persistent launches from a
+ * cached work list: one launch per tile group (see fwht_set_batched_tiles;
+ * by default one group, hence one launch), issued directly on `stream`, or
+ * replayed from a HIP graph captured once per request when
+ * fwht_set_batched_graphs(1) is in effect.
  *   data    : device FP32 buffer; transform t occupies
  *             data[offsets[t] .. offsets[t] + 2^log2n[t]).
  *   offsets : HOST array [count] of entry offsets (each a multiple of 4).
  *   log2n   : HOST array [count], each in [2, 16] (FWHT_E_RANGE otherwise).
  * offsets and log2n are host arrays (not device arrays): the work list is
  * built from them on the host on the first call with a given (data, count,
- * normalize, prec, tile groups, contents of offsets/log2n) and cached with
- * its graph, together with a copy of both arrays; a later call whose
- * arguments equal a cached request element for element only replays that
- * graph on `stream`.
+ * normalize, prec, tile groups, contents of offsets/log2n) and cached in
+ * device memory, together with a copy of both arrays; a later call whose
+ * arguments equal a cached request element for element only compares them
+ * and launches the cached work list (or replays its graph) on `stream`.
  * Transforms must not overlap.  Errors: FWHT_E_INVAL, FWHT_E_RANGE,
  * FWHT_E_NOMEM, FWHT_E_HIP.  Not thread-safe with itself. */
 int fwht_batched(float *data, const int64_t *offsets, const int32_t *log2n, int32_t count,
@@ -148,7 +150,7 @@ int fwht_batched_noalloc(float *data, const int64_t *offsets, const int32_t *log
  * 2^15-entry tiles of 512 threads, two workgroups per CU); a group is
  * "tb:lo-hi" or "tb:m", tb in {14, 15, 16} (only 16 for the matrix-core
  * precisions), every size 2^2 .. 2^16 in exactly one group, at most three
- * groups.  Each group is one persistent launch of the request's graph.
+ * groups.  Each group is one persistent launch.
  * spec = NULL restores the default (the tuned table's "batched" line, else
  * "16:2-16").  Used by the autotuner.  Results are the same transform; FP32
  * rounding differs between tile sizes.  Returns FWHT_E_INVAL for a bad spec. */
@@ -157,6 +159,19 @@ int fwht_set_batched_tiles(int prec, const char *spec);
 /* The tile groups in use for `prec`, written to buf (NUL-terminated);
  * FWHT_E_CAPACITY if len is too small. */
 int fwht_get_batched_tiles(int prec, char *buf, int len);
+
+/* How fwht_batched issues a cached request, for every later call of the
+ * process: on = 0 (the default) launches the persistent kernels of its work
+ * list directly on the stream; on != 0 replays a HIP graph captured from
+ * those launches (captured at the first such call of each request).  The
+ * results are identical; on the measured stack a graph replay of one kernel
+ * costs about 15 us of host time and 12 us more latency than the direct
+ * launch, so graphs pay only where the caller batches them further.
+ * Returns FWHT_OK. */
+int fwht_set_batched_graphs(int on);
+
+/* The current fwht_set_batched_graphs setting (0 or 1). */
+int fwht_get_batched_graphs(void);
 
 /* Stand-alone threshold pass over 2^n already-transformed device entries of
  * dtype `dtype` (I32/I64 compare |W_k| > th->T exactly in 64 bits; F32

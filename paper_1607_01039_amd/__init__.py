@@ -29,7 +29,8 @@ PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
               "bf16": _lib.FWHT_PREC_BF16_MFMA}
 
 __all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "fwht_batched_noalloc_", "threshold", "fwht", "FWHTFunction",
-           "norms", "set_schedule", "get_schedule", "set_batched_tiles", "get_batched_tiles", "trace_enable",
+           "norms", "set_schedule", "get_schedule", "set_batched_tiles", "get_batched_tiles", "set_batched_graphs",
+           "get_batched_graphs", "trace_enable",
            "trace_read", "copy_",
            "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "subspace_scan", "prime_omega",
            "FWHTError", "PRECISIONS"]
@@ -281,13 +282,13 @@ def fwht_batched_(data, offsets, log2n, normalize: bool = True, precision: str =
     ``offsets`` (int64) and ``log2n`` (int32) are host arrays (numpy or CPU
     tensors): transform t is data[offsets[t] : offsets[t] + 2^log2n[t]].
     """
-    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
-    lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    lg = np.ascontiguousarray(log2n, dtype=np.int32)
     if off.shape != lg.shape:
         raise ValueError("offsets and log2n must have the same length")
-    _lib.check(_lib.lib().fwht_batched(C.c_void_p(data.data_ptr()), off.ctypes.data_as(C.c_void_p),
-                                       lg.ctypes.data_as(C.c_void_p), len(off), int(bool(normalize)),
-                                       PRECISIONS[precision], _stream_ptr(data)))
+    # raw addresses (ctypes' data_as costs microseconds per call)
+    _lib.check(_lib.lib().fwht_batched(data.data_ptr(), off.ctypes.data, lg.ctypes.data, len(off),
+                                       int(bool(normalize)), PRECISIONS[precision], _stream_ptr(data)))
     return data
 
 
@@ -295,13 +296,12 @@ def fwht_batched_noalloc_(data, offsets, log2n, normalize: bool = True, precisio
     """``fwht_batched_`` through the entry point that allocates nothing (a
     fixed work-list array of the library per GPU; at most 65536 transforms;
     calls on one GPU must not overlap)."""
-    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
-    lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    lg = np.ascontiguousarray(log2n, dtype=np.int32)
     if off.shape != lg.shape:
         raise ValueError("offsets and log2n must have the same length")
-    _lib.check(_lib.lib().fwht_batched_noalloc(C.c_void_p(data.data_ptr()), off.ctypes.data_as(C.c_void_p),
-                                               lg.ctypes.data_as(C.c_void_p), len(off), int(bool(normalize)),
-                                               PRECISIONS[precision], _stream_ptr(data)))
+    _lib.check(_lib.lib().fwht_batched_noalloc(data.data_ptr(), off.ctypes.data, lg.ctypes.data, len(off),
+                                               int(bool(normalize)), PRECISIONS[precision], _stream_ptr(data)))
     return data
 
 
@@ -385,6 +385,16 @@ def get_batched_tiles(precision: str = "fp32") -> str:
     buf = C.create_string_buffer(256)
     _lib.check(_lib.lib().fwht_get_batched_tiles(PRECISIONS[precision], buf, 256))
     return buf.value.decode()
+
+
+def set_batched_graphs(on: bool) -> None:
+    """Issue cached batched requests as HIP graph replays (True) or as direct
+    launches of their work list (False, the default)."""
+    _lib.check(_lib.lib().fwht_set_batched_graphs(int(bool(on))))
+
+
+def get_batched_graphs() -> bool:
+    return bool(_lib.lib().fwht_get_batched_graphs())
 
 
 def _make_function():

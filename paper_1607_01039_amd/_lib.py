@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "FWHT_OK", 1: "FWHT_E_INVAL", 2: "FWHT_E_RANGE", 3: "FWHT_E_C
 EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
            "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_trace_enable", "fwht_trace_read",
            "fwht_copy", "fwht_fold", "fwht_fold_planted", "fwht_subspace_hits", "fwht_prime_omega", "fwht_last_error",
-           "fwht_version", "fwht_set_batched_tiles", "fwht_get_batched_tiles")
+           "fwht_version", "fwht_set_batched_tiles", "fwht_get_batched_tiles", "fwht_set_batched_graphs",
+           "fwht_get_batched_graphs")
 
 
 class fwht_thresh_t(C.Structure):
@@ -60,6 +61,8 @@ def lib() -> C.CDLL:
     L.fwht_batched_noalloc.argtypes = [vp, vp, vp, C.c_int32, i32, i32, vp]
     L.fwht_set_batched_tiles.argtypes = [i32, C.c_char_p]
     L.fwht_get_batched_tiles.argtypes = [i32, C.c_char_p, i32]
+    L.fwht_set_batched_graphs.argtypes = [i32]
+    L.fwht_get_batched_graphs.argtypes = []
     L.fwht_threshold.argtypes = [vp, i32, i32, C.POINTER(fwht_thresh_t), vp]
     L.fwht_norms.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp]
     L.fwht_set_schedule.argtypes = [i32, i32, C.c_char_p]
@@ -77,7 +80,8 @@ def lib() -> C.CDLL:
     for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
                  "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_copy",
                  "fwht_trace_enable", "fwht_trace_read", "fwht_fold", "fwht_fold_planted",
-                 "fwht_subspace_hits", "fwht_prime_omega", "fwht_set_batched_tiles", "fwht_get_batched_tiles"):
+                 "fwht_subspace_hits", "fwht_prime_omega", "fwht_set_batched_tiles", "fwht_get_batched_tiles",
+                 "fwht_set_batched_graphs", "fwht_get_batched_graphs"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -7,12 +7,18 @@
 // tiles in 1024 threads, one workgroup per CU; 2^15 tiles in 512 threads and
 // 2^14 tiles in 256 threads, two and four workgroups per CU, so that one
 // workgroup's loads and stores overlap another's LDS phases).  Each group is
-// one persistent launch; the launches of a request are captured in one graph.
+// one persistent launch.  A request's work list is built and uploaded once
+// and cached; later calls with the same request launch its kernels straight
+// from the cached list, or (fwht_set_batched_graphs) replay a HIP graph
+// captured from those launches.  Direct launches are the default: measured
+// on this stack, replaying a one-kernel graph costs 15 us of host time and
+// 12 us more latency than launching the kernel itself (2.5 us and 6.8 us).
 // The FP32 grouping comes from the tuned table ("batched fp32 <groups>") or
 // fwht_set_batched_tiles; the matrix-core kernels use 2^16 tiles only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -164,14 +170,15 @@ struct Plan {
     float *data = nullptr;
     int32_t count = 0;
     int normalize = 0, prec = 0;
-    uint64_t hash = 0;
     TilePlan tiles;
-    std::vector<int64_t> off;  // the request itself, compared on a hash match
+    std::vector<int64_t> off;  // the request itself
     std::vector<int32_t> lg;
     // device state
     BItem *items = nullptr;
     int64_t *segs = nullptr;
-    hipGraphExec_t exec = nullptr;
+    GroupRange gr[3];
+    int grid[3] = {0, 0, 0};
+    hipGraphExec_t exec = nullptr;  // captured on the first replay in graph mode
     hipGraph_t graph = nullptr;
 };
 
@@ -179,27 +186,7 @@ std::mutex g_mu;
 std::list<Plan> g_plans;  // most recent first
 constexpr size_t kMaxPlans = 8;
 hipStream_t g_capture = nullptr;
-
-// Cache key of the host arrays: a multiply-xorshift hash over 8-byte words
-// (a byte-wise hash of 4096 offsets and sizes took tens of microseconds,
-// spent on the host before every replay).  A plan matches only when the
-// hash and then the stored arrays themselves are equal, so a collision can
-// never replay another request's graph.
-uint64_t hash_words(const void *p, size_t n, uint64_t h)
-{
-    const unsigned char *c = (const unsigned char *)p;
-    size_t i = 0;
-    for (; i + 8 <= n; i += 8) {
-        uint64_t w;
-        memcpy(&w, c + i, 8);
-        h = (h ^ w) * 0x9E3779B97F4A7C15ull;
-        h ^= h >> 29;
-    }
-    uint64_t w = 0;
-    memcpy(&w, c + i, n - i);
-    h = (h ^ w ^ (uint64_t)n) * 0x9E3779B97F4A7C15ull;
-    return h ^ (h >> 31);
-}
+std::atomic<int> g_use_graphs{0};
 
 void release(Plan &p)
 {
@@ -210,13 +197,12 @@ void release(Plan &p)
     p = Plan{};
 }
 
-int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32_t count, int normalize, int prec)
+int make_plan(Plan &p, const int64_t *off, const int32_t *lg, int32_t count, int prec)
 {
     std::vector<BItem> items((size_t)count);
     std::vector<int64_t> segs((size_t)count);
-    GroupRange gr[3];
-    build_work_list(p.tiles, off, lg, count, items.data(), segs.data(), gr);
-    const size_t nitems = (size_t)(gr[p.tiles.n - 1].item0 + gr[p.tiles.n - 1].nitems);
+    build_work_list(p.tiles, off, lg, count, items.data(), segs.data(), p.gr);
+    const size_t nitems = (size_t)(p.gr[p.tiles.n - 1].item0 + p.gr[p.tiles.n - 1].nitems);
     hipError_t e = hipMalloc(&p.items, sizeof(BItem) * nitems);
     if (e == hipSuccess) e = hipMalloc(&p.segs, sizeof(int64_t) * segs.size());
     if (e != hipSuccess) return fail(FWHT_E_NOMEM, "batched plan: %s", hipGetErrorString(e));
@@ -224,21 +210,27 @@ int make_plan(Plan &p, float *data, const int64_t *off, const int32_t *lg, int32
     if (e == hipSuccess) e = hipMemcpy(p.segs, segs.data(), sizeof(int64_t) * segs.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "batched plan upload");
 
-    int grid[3] = {0, 0, 0};
     for (int gi = 0; gi < p.tiles.n; ++gi) {
-        const int rc = grid_size(prec, p.tiles.g[gi].tb, &grid[gi]);
+        const int rc = grid_size(prec, p.tiles.g[gi].tb, &p.grid[gi]);
         if (rc) return rc;
     }
+    return FWHT_OK;
+}
+
+// The graph of a plan: the persistent launch of each group, one after another
+// (work is assigned statically, so there is no counter to reset between
+// replays).
+int capture_graph(Plan &p)
+{
+    hipError_t e = hipSuccess;
     if (!g_capture) {
         e = hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "capture stream");
     }
-    // The graph: the persistent launch of each group, one after another
-    // (work is assigned statically, so there is no counter to reset between
-    // replays).
     e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "begin capture");
-    const hipError_t le = launch_work_list(prec, p.tiles, gr, grid, data, p.items, p.segs, normalize, g_capture);
+    const hipError_t le =
+        launch_work_list(p.prec, p.tiles, p.gr, p.grid, p.data, p.items, p.segs, p.normalize, g_capture);
     e = hipStreamEndCapture(g_capture, &p.graph);
     if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
     if (e != hipSuccess) return hip_fail(e, "end capture");
@@ -309,15 +301,15 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
             hipStream_t s)
 {
     const TilePlan tiles = tiles_for(prec);
-    uint64_t h = hash_words(off, sizeof(int64_t) * (size_t)count, 0xcbf29ce484222325ull);
-    h = hash_words(lg, sizeof(int32_t) * (size_t)count, h);
     std::lock_guard<std::mutex> lk(g_mu);
+    // A plan matches only when its request is the same, arrays included: a
+    // straight comparison (1 us for 4096 transforms) costs less than any
+    // hash of them, whose dependency chain took 13 us.
     auto it = g_plans.begin();
     for (; it != g_plans.end(); ++it)
         if (it->data == data && it->count == count && it->normalize == normalize && it->prec == prec &&
-            it->hash == h && same_tiles(it->tiles, tiles) &&
-            !memcmp(it->off.data(), off, sizeof(int64_t) * (size_t)count) &&
-            !memcmp(it->lg.data(), lg, sizeof(int32_t) * (size_t)count))
+            same_tiles(it->tiles, tiles) && !memcmp(it->lg.data(), lg, sizeof(int32_t) * (size_t)count) &&
+            !memcmp(it->off.data(), off, sizeof(int64_t) * (size_t)count))
             break;
     if (it == g_plans.end()) {
         if (g_plans.size() >= kMaxPlans) {
@@ -332,11 +324,10 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
         p.count = count;
         p.normalize = normalize;
         p.prec = prec;
-        p.hash = h;
         p.tiles = tiles;
         p.off.assign(off, off + count);
         p.lg.assign(lg, lg + count);
-        int rc = make_plan(p, data, off, lg, count, normalize, prec);
+        int rc = make_plan(p, off, lg, count, prec);
         if (rc) {
             release(p);
             g_plans.pop_front();
@@ -347,8 +338,17 @@ int batched(float *data, const int64_t *off, const int32_t *lg, int32_t count, i
         g_plans.splice(g_plans.begin(), g_plans, it);
         it = g_plans.begin();
     }
-    hipError_t e = hipGraphLaunch(it->exec, s);
-    return e == hipSuccess ? FWHT_OK : hip_fail(e, "graph launch");
+    if (g_use_graphs.load(std::memory_order_relaxed)) {
+        if (!it->exec) {
+            const int rc = capture_graph(*it);
+            if (rc) return rc;
+        }
+        const hipError_t e = hipGraphLaunch(it->exec, s);
+        return e == hipSuccess ? FWHT_OK : hip_fail(e, "graph launch");
+    }
+    const hipError_t e =
+        launch_work_list(prec, it->tiles, it->gr, it->grid, data, it->items, it->segs, normalize, s);
+    return e == hipSuccess ? FWHT_OK : hip_fail(e, "batched launch");
 }
 
 }  // namespace fwht
@@ -483,3 +483,11 @@ extern "C" int fwht_get_batched_tiles(int prec, char *buf, int len)
     memcpy(buf, s.c_str(), s.size() + 1);
     return FWHT_OK;
 }
+
+extern "C" int fwht_set_batched_graphs(int on)
+{
+    fwht::g_use_graphs.store(on != 0, std::memory_order_relaxed);
+    return FWHT_OK;
+}
+
+extern "C" int fwht_get_batched_graphs(void) { return fwht::g_use_graphs.load(std::memory_order_relaxed); }

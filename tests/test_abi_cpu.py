@@ -222,3 +222,11 @@ def test_batched_tile_groups_parsing(L):
     assert L.fwht_set_batched_tiles(0, None) == 0 and L.fwht_set_batched_tiles(1, None) == 0
     small = C.create_string_buffer(3)
     assert L.fwht_get_batched_tiles(0, small, 3) == _lib.FWHT_E_CAPACITY
+
+
+def test_batched_launch_mode_switch(L):
+    """Direct launches by default; the graph-replay setting reads back and restores."""
+    assert L.fwht_get_batched_graphs() == 0
+    assert L.fwht_set_batched_graphs(1) == 0 and L.fwht_get_batched_graphs() == 1
+    assert L.fwht_set_batched_graphs(7) == 0 and L.fwht_get_batched_graphs() == 1
+    assert L.fwht_set_batched_graphs(0) == 0 and L.fwht_get_batched_graphs() == 0

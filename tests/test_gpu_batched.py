@@ -1,5 +1,6 @@
 """GPU parity of the batched persistent transform (uneven sizes, one launch
-replayed from a cached HIP graph) against the FP64 oracle.
+per call from a cached work list, directly or as a HIP graph replay) against
+the FP64 oracle.
 
 FP32 tolerance as for fwht_float: normwise (m + 2) * 2^-23 per transform.
 """
@@ -81,23 +82,42 @@ def test_batched_config_4096(F, O):
     assert np.all(errs <= (lg + 2) * 2.0 ** -23), errs.max()
 
 
-def test_batched_graph_replays(F, O):
-    """The cached graph is replayed several times with eager work and syncs in
-    between; every replay must give the eager result (Y(Yx) = x after two)."""
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batched_graph_replays(F, O, graphs):
+    """A cached request is issued several times (direct launches, or replays of
+    its captured graph) with eager work and syncs in between; every call must
+    give the eager result (Y(Yx) = x after two), and the other mode, on the
+    same input, the same bits as this mode's first call."""
     import torch
     lg, off, tot = synth.ragged(500, 2, 16, 7)
     x = synth.normal(tot, 7)
     ref1 = O.wht_ragged(x, off, lg, True)
     t = torch.from_numpy(x).cuda()
-    for rep in range(6):
-        F.fwht_batched_(t, off, lg)
-        junk = torch.randn(1 << 20, device="cuda")  # eager work between replays
-        junk.mul_(2.0).sum().item()
-        torch.cuda.synchronize()
-        y = t.cpu().numpy()
-        want = ref1 if rep % 2 == 0 else x.astype(np.float64)
-        errs = per_transform_err(y, want, off, lg)
-        assert np.all(errs <= 2 * (lg + 2) * 2.0 ** -23), (rep, errs.max())
+    prev = F.get_batched_graphs()
+    F.set_batched_graphs(graphs)
+    try:
+        assert F.get_batched_graphs() == graphs
+        outs = []
+        for rep in range(6):
+            F.fwht_batched_(t, off, lg)
+            junk = torch.randn(1 << 20, device="cuda")  # eager work between calls
+            junk.mul_(2.0).sum().item()
+            torch.cuda.synchronize()
+            y = t.cpu().numpy()
+            outs.append(y)
+            want = ref1 if rep % 2 == 0 else x.astype(np.float64)
+            errs = per_transform_err(y, want, off, lg)
+            assert np.all(errs <= 2 * (lg + 2) * 2.0 ** -23), (rep, errs.max())
+    finally:
+        F.set_batched_graphs(prev)
+    # the other mode on the same cached request: bit-identical first result
+    F.set_batched_graphs(not graphs)
+    try:
+        t2 = torch.from_numpy(x).cuda()
+        F.fwht_batched_(t2, off, lg)
+        assert np.array_equal(t2.cpu().numpy(), outs[0])
+    finally:
+        F.set_batched_graphs(prev)
 
 
 def test_batched_permutation_invariant(F, O):
