@@ -166,7 +166,10 @@ def tune(dtype: str, ns, min_total_bits: int = 0, log=print):
         best = None
         t0 = time.time()
         for spec in cands:
-            ms = time_schedule(F, torch, buf, dtype, n, spec, src=src)
+            try:
+                ms = time_schedule(F, torch, buf, dtype, n, spec, src=src)
+            except F.FWHTError:
+                continue  # refused by the library (e.g. a pass whose lane offsets would not fit 32 bits)
             if best is None or ms < best[1]:
                 best = (spec, ms)
         F.set_schedule(dtype, n, None)

@@ -2,6 +2,7 @@
 // library.  Arguments are validated on the host before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -62,6 +63,28 @@ static const Variant *find_variant(int dtype, const std::string &name)
 static std::mutex g_sched_mu;
 static std::map<std::pair<int, int>, std::string> g_sched_override;
 
+// A strided tile pass keeps each lane's offset from the wave's row-segment
+// base in 32 bits (bytes).  In a layout that reaches global memory (the load
+// layout, and every layout the pass may store from) the lane bits can include
+// row bits, each worth 2^b entries, so at a large row stride b that offset
+// no longer fits: such (variant, b) pairs are refused.  The register-resident
+// kernels keep 64-bit lane offsets, and contiguous passes have b = CB.
+static bool lane_offsets_fit(const Variant &v, int b, int dtype)
+{
+    if (v.whole || v.cols) return true;
+    const uint32_t esz = dtype == FWHT_I64 ? 8u : 4u;
+    const int K = clog2((1u << v.TB) / (uint32_t)v.NT), VB = clog2(16u / esz);
+    const LayoutList L = make_layouts(v.TB, v.CB, K, VB, false);
+    const int slb = std::min(8 - clog2(esz), v.CB);
+    for (int p = 0; p < L.n; ++p) {
+        if (p > 0 && !lanes_contiguous(L.m[p], slb)) continue;
+        const uint32_t lane = low_set_bits(lowmask(v.TB) & ~L.m[p], 6);
+        const uint64_t top = (((uint64_t)(lane >> v.CB)) << b) + (lane & lowmask(v.CB));
+        if (top * esz >= (1ull << 32)) return false;
+    }
+    return true;
+}
+
 bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass> &out, std::string &why)
 {
     out.clear();
@@ -95,6 +118,10 @@ bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass>
         }
         if (v->whole && !v->cols && r != cap) {
             why = "a register-resident strided variant covers exactly its full height";
+            return false;
+        }
+        if (!lane_offsets_fit(*v, done, dtype)) {
+            why = tok + " at bit " + std::to_string(done) + ": lane offsets of its row stride exceed 32 bits";
             return false;
         }
         out.push_back(Pass{v, done, r});
@@ -255,8 +282,9 @@ int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, c
     if (nbits <= 0) return FWHT_OK;
     const int tbmax = dtype == FWHT_I64 ? 14 : 15, cbmax = dtype == FWHT_I64 ? 7 : 8;
     const int np = (nbits + 8) / 9;
-    int done = lo;
-    for (int i = 0; i < np; ++i) {
+    // every pass is chosen and checked before the first one is launched
+    std::vector<Pass> passes;
+    for (int i = 0, done = lo; i < np; ++i) {
         const int r = nbits / np + (i < nbits % np ? 1 : 0);
         // the widest row segment that fits the tile and lies below bit `done`
         int c = tbmax - r < cbmax ? tbmax - r : cbmax;
@@ -265,6 +293,14 @@ int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, c
         for (; c >= 4 && !v; --c) v = find_variant(dtype, "S" + std::to_string(c + r) + "c" + std::to_string(c));
         if (!v) return fail(FWHT_E_UNSUPPORTED, "no strided variant for %d bits at bit %d", r, done);
         if (done < v->CB) return fail(FWHT_E_INVAL, "strided range starts below the row segment");
+        if (!lane_offsets_fit(*v, done, dtype))
+            return fail(FWHT_E_UNSUPPORTED, "%s at bit %d: lane offsets exceed 32 bits", v->name, done);
+        passes.push_back(Pass{v, done, r});
+        done += r;
+    }
+    for (int i = 0; i < np; ++i) {
+        const Variant *v = passes[i].v;
+        const int done = passes[i].lo, r = passes[i].r;
         PassArgs a{};
         a.total = total;
         a.b = done;
@@ -288,7 +324,6 @@ int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, c
         }
         hipError_t e = v->launch(buf, a, s);
         if (e != hipSuccess) return hip_fail(e, "strided pass launch");
-        done += r;
     }
     return FWHT_OK;
 }

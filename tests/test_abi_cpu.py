@@ -79,7 +79,8 @@ def test_schedule_parsing(L):
     from paper_1607_01039_amd import _lib
     ok = [(0, 30, b"C14,S14c6,S14c6"), (0, 20, b"C12,S14c6:8"), (1, 25, b"C13,S13c5,S13c5:4"),
           (2, 16, b"C15:10,S12c5:6"), (0, 30, b"C16,S15c8:7,S15c8:7"), (2, 17, b"C16,S9c8:1"),
-          (0, 30, b"C15pn,S15c8n:7,S16c8n:8"), (2, 20, b"C15p,S13c8:5")]
+          (0, 30, b"C15pn,S15c8n:7,S16c8n:8"), (2, 20, b"C15p,S13c8:5"),
+          (1, 30, b"C14pn,S14c5n:9,S13c6:5,S12c6:2"), (1, 34, b"C14pn,S14c7:7,S14c7:7,S13c7:6")]
     for dt, n, spec in ok:
         assert L.fwht_set_schedule(dt, n, spec) == 0, (spec, L.fwht_last_error())
         buf = C.create_string_buffer(128)
@@ -87,7 +88,9 @@ def test_schedule_parsing(L):
         assert L.fwht_set_schedule(dt, n, None) == 0
     bad = [(0, 30, b"C14,S14c6"), (0, 20, b"S14c6,C14"), (0, 20, b"X9"), (0, 20, b"C14:0,S14c6"),
            (0, 20, b"C12:3,S14c6,S14c6"), (0, 16, b"C16"), (0, 20, b"C16:12,S12c8:8"), (2, 16, b"C16"), (0, 15, b"C15p"),
-           (0, 20, b"C15p:12,S12c8:8"), (1, 20, b"C15p,S13c8:5")]
+           (0, 20, b"C15p:12,S12c8:8"), (1, 20, b"C15p,S13c8:5"),
+           # 8-byte entries: lane offsets of a row bit at stride 2^29 (2^32 bytes) no longer fit 32 bits
+           (1, 30, b"C14pn,S14c5n:9,S13c6:6,S12c6:1"), (1, 32, b"C13,S13c5:8,S13c5:8,S13c5:3")]
     for dt, n, spec in bad:
         assert L.fwht_set_schedule(dt, n, spec) == _lib.FWHT_E_INVAL, spec
 

@@ -362,6 +362,30 @@ def test_int64_default_schedule(F, O, n):
     _default_schedule_parity(F, O, "int64", n, x)
 
 
+@pytest.mark.parametrize("n,spec", [(29, "C14pn,S14c5n:9,S13c6:5,S12c6:1"), (30, "C14pn,S14c5n:9,S13c6:5,S12c6:2")])
+def test_int64_lane_offset_boundary(F, O, n, spec):
+    """A strided tile pass keeps lane offsets in 32 bits: S12c6 (one row bit
+    among its lane bits) at row stride 2^28 is the largest accepted stride for
+    8-byte entries (2^28 * 8 = 2^31 bytes), and every entry must still match
+    the oracle there; one bit further up the library refuses it."""
+    import torch
+    x = synth.raw64(1 << n, 4300 + n)
+    F.set_schedule("int64", n, spec)
+    try:
+        t = _upload(x)
+        F.fwht_int_(t)
+        torch.cuda.synchronize()
+    finally:
+        F.set_schedule("int64", n, None)
+    O.wht_fig2_inplace(x, 4)
+    bad = _equal_chunks(t, x)
+    del t
+    torch.cuda.empty_cache()
+    assert bad is None, f"first differing chunk at entry {bad}"
+    with pytest.raises(F.FWHTError, match="lane offsets"):
+        F.set_schedule("int64", 30, "C14pn,S14c5n:9,S13c6:6,S12c6:1")  # S12c6 at 2^29
+
+
 @pytest.mark.parametrize("n", [33, 34])
 def test_int64_large_in_hbm(F, O, n):
     """int64 up to the in-HBM limit (n = 34: 128 GiB resident), planted peak
