@@ -104,6 +104,16 @@ int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream
  * 4 <= n <= 16 (otherwise FWHT_E_UNSUPPORTED). */
 int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void *stream);
 
+/* fwht_float out of place: dst = transform of src, src unchanged (both device
+ * pointers, 16-byte aligned, batch * 2^n FP32 entries each; they must not
+ * overlap unless src == dst, which is fwht_float on dst).  FP32: the first
+ * pass reads src and writes dst, the others work in place on dst, so it
+ * moves the same bytes as the in-place transform and no copy is made; the
+ * matrix-core precisions (and n = 0) copy src to dst on `stream` first.
+ * Results equal fwht_float's on a copy of src, bit for bit.  Errors as
+ * fwht_float, plus FWHT_E_INVAL for overlapping buffers. */
+int fwht_float_out(const float *src, float *dst, int n, int64_t batch, int normalize, int prec, void *stream);
+
 /* In-place float WHT of `count` independent transforms of uneven sizes
  * (the orthonormal or unnormalised Eq. 2 of each; batching is this
  * library's extension, not the paper's) in persistent launches from a

@@ -28,8 +28,8 @@ from ._lib import FWHTError
 PRECISIONS = {"fp32": _lib.FWHT_PREC_FP32, "fp16": _lib.FWHT_PREC_FP16_MFMA,
               "bf16": _lib.FWHT_PREC_BF16_MFMA}
 
-__all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_batched_", "fwht_batched_noalloc_", "threshold", "fwht", "FWHTFunction",
-           "norms", "set_schedule", "get_schedule", "set_batched_tiles", "get_batched_tiles", "set_batched_graphs",
+__all__ = ["fwht_int_", "hit_buffers", "fwht_float_", "fwht_float_out", "fwht_batched_", "fwht_batched_noalloc_",
+           "threshold", "fwht", "FWHTFunction", "norms", "set_schedule", "get_schedule", "set_batched_tiles", "get_batched_tiles", "set_batched_graphs",
            "get_batched_graphs", "trace_enable",
            "trace_read", "copy_",
            "fold_", "fold_planted", "subspace_hits_", "subspace_transform", "subspace_scan", "prime_omega",
@@ -276,6 +276,23 @@ def fwht_float_(t, normalize: bool = True, precision: str = "fp32"):
     return t
 
 
+def fwht_float_out(src, out=None, normalize: bool = True, precision: str = "fp32"):
+    """Out-of-place float WHT over the last dimension: returns ``out`` (a new
+    tensor if None) holding the transform of ``src``, which is left unchanged."""
+    torch = _torch()
+    if src.dtype != torch.float32 or not src.is_cuda or not src.is_contiguous():
+        raise TypeError("fwht_float_out needs a contiguous float32 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(src)
+    elif out.shape != src.shape or out.dtype != src.dtype or not out.is_contiguous() or out.device != src.device:
+        raise TypeError("out must be a contiguous float32 tensor of src's shape on its device")
+    n = _log2(src.shape[-1])
+    batch = src.numel() >> n
+    _lib.check(_lib.lib().fwht_float_out(src.data_ptr(), out.data_ptr(), n, batch, int(bool(normalize)),
+                                         PRECISIONS[precision], _stream_ptr(src)))
+    return out
+
+
 def fwht_batched_(data, offsets, log2n, normalize: bool = True, precision: str = "fp32"):
     """In-place WHT of uneven transforms packed in a float32 CUDA tensor.
 
@@ -408,15 +425,11 @@ def _make_function():
         @staticmethod
         def forward(ctx, x, precision="fp32"):
             ctx.precision = precision
-            y = x.contiguous().clone()
-            fwht_float_(y, True, precision)
-            return y
+            return fwht_float_out(x.contiguous(), None, True, precision)
 
         @staticmethod
         def backward(ctx, g):
-            gx = g.contiguous().clone()
-            fwht_float_(gx, True, ctx.precision)
-            return gx, None
+            return fwht_float_out(g.contiguous(), None, True, ctx.precision), None
 
     return FWHTFunction
 

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "FWHT_OK", 1: "FWHT_E_INVAL", 2: "FWHT_E_RANGE", 3: "FWHT_E_C
                 4: "FWHT_E_NOMEM", 5: "FWHT_E_HIP", 6: "FWHT_E_UNSUPPORTED"}
 
 # Every symbol include/fwht.h declares.
-EXPORTS = ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
+EXPORTS = ("fwht_int", "fwht_float", "fwht_float_out", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
            "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_trace_enable", "fwht_trace_read",
            "fwht_copy", "fwht_fold", "fwht_fold_planted", "fwht_subspace_hits", "fwht_prime_omega", "fwht_last_error",
            "fwht_version", "fwht_set_batched_tiles", "fwht_get_batched_tiles", "fwht_set_batched_graphs",
@@ -57,6 +57,7 @@ def lib() -> C.CDLL:
     vp, i32, i64, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64
     L.fwht_int.argtypes = [vp, i32, i32, C.POINTER(fwht_thresh_t), vp]
     L.fwht_float.argtypes = [vp, i32, i64, i32, i32, vp]
+    L.fwht_float_out.argtypes = [vp, vp, i32, i64, i32, i32, vp]
     L.fwht_batched.argtypes = [vp, vp, vp, C.c_int32, i32, i32, vp]
     L.fwht_batched_noalloc.argtypes = [vp, vp, vp, C.c_int32, i32, i32, vp]
     L.fwht_set_batched_tiles.argtypes = [i32, C.c_char_p]
@@ -77,7 +78,7 @@ def lib() -> C.CDLL:
     L.fwht_prime_omega.argtypes = [vp, i32, i32, vp]
     L.fwht_last_error.restype = C.c_char_p
     L.fwht_version.restype = C.c_char_p
-    for name in ("fwht_int", "fwht_float", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
+    for name in ("fwht_int", "fwht_float", "fwht_float_out", "fwht_batched", "fwht_batched_noalloc", "fwht_threshold", "fwht_norms",
                  "fwht_set_schedule", "fwht_get_schedule", "fwht_list_variants", "fwht_copy",
                  "fwht_trace_enable", "fwht_trace_read", "fwht_fold", "fwht_fold_planted",
                  "fwht_subspace_hits", "fwht_prime_omega", "fwht_set_batched_tiles", "fwht_get_batched_tiles",

@@ -58,7 +58,10 @@ std::vector<Variant> variants_f32();
 bool parse_schedule(int dtype, int n, const std::string &spec, std::vector<Pass> &out, std::string &why);
 std::string schedule_for(int dtype, int n);
 const std::string *tuned_schedule(int dtype, int n);
-int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s);
+// src != nullptr: the first pass reads src and writes buf (out of place; the
+// two must not overlap), the others work in place on buf
+int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s,
+               const void *src = nullptr);
 int run_strided_range(void *buf, int dtype, uint64_t total, int lo, int nbits, const Epilogue &epi, hipStream_t s);
 int zero_count(uint64_t *count, hipStream_t s);
 float float_threshold(double T);

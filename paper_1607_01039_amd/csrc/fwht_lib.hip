@@ -199,7 +199,7 @@ static hipError_t trace_record(int i, hipStream_t s)
 }
 
 // Enqueue the passes of a transform of `batch` x 2^n entries.
-int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s)
+int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi, hipStream_t s, const void *src)
 {
     if (n == 0) return FWHT_OK;
     std::vector<Pass> passes;
@@ -260,7 +260,12 @@ int run_passes(void *buf, int dtype, int n, uint64_t batch, const Epilogue &epi,
             a.cap = epi.cap;
             a.count = (unsigned long long *)epi.count;
         }
-        hipError_t e = v.launch(buf, a, s);
+        void *from = buf;
+        if (p == 0 && src) {
+            from = const_cast<void *>(src);  // read only by the kernel
+            a.dst = buf;
+        }
+        hipError_t e = v.launch(from, a, s);
         if (e != hipSuccess) return hip_fail(e, "pass launch");
         if (tr) {
             e = trace_record((int)p + 1, s);
@@ -461,6 +466,35 @@ int fwht_float(float *data, int n, int64_t batch, int normalize, int prec, void 
         epi.scale = (float)(1.0 / std::sqrt(std::ldexp(1.0, n)));
     }
     return run_passes(data, FWHT_F32, n, (uint64_t)batch, epi, s);
+}
+
+int fwht_float_out(const float *src, float *dst, int n, int64_t batch, int normalize, int prec, void *stream)
+{
+    g_err.clear();
+    if (!src || !dst) return fail(FWHT_E_INVAL, "src or dst is NULL");
+    if ((((uintptr_t)src) | ((uintptr_t)dst)) & 15) return fail(FWHT_E_INVAL, "src and dst must be 16-byte aligned");
+    if (n < 0 || n > 30) return fail(FWHT_E_RANGE, "fwht_float_out needs 0 <= n <= 30");
+    if (batch < 1) return fail(FWHT_E_INVAL, "batch must be >= 1");
+    if (n + 64 - __builtin_clzll((unsigned long long)batch) > 40) return fail(FWHT_E_RANGE, "batch * 2^n too large");
+    if (prec != FWHT_PREC_FP32 && prec != FWHT_PREC_FP16_MFMA && prec != FWHT_PREC_BF16_MFMA)
+        return fail(FWHT_E_INVAL, "unknown precision %d", prec);
+    if (src == dst) return fwht_float(dst, n, batch, normalize, prec, stream);
+    const uint64_t bytes = ((uint64_t)batch << n) * sizeof(float);
+    const uintptr_t a0 = (uintptr_t)src, b0 = (uintptr_t)dst;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(FWHT_E_INVAL, "src and dst overlap");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec != FWHT_PREC_FP32 || n == 0) {
+        // the matrix-core kernels work in place: copy, then transform dst
+        const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "copy src to dst");
+        return fwht_float(dst, n, batch, normalize, prec, stream);
+    }
+    Epilogue epi{};
+    if (normalize) {
+        epi.do_scale = 1;
+        epi.scale = (float)(1.0 / std::sqrt(std::ldexp(1.0, n)));
+    }
+    return run_passes(dst, FWHT_F32, n, (uint64_t)batch, epi, s, src);
 }
 
 int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, void *stream)

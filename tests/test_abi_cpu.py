@@ -64,6 +64,17 @@ def test_float_validation(L):
     assert L.fwht_float(C.c_void_p(p), 4, 0, 1, 0, None) == _lib.FWHT_E_INVAL
     assert L.fwht_float(C.c_void_p(p), 30, 1 << 12, 1, 0, None) == _lib.FWHT_E_RANGE
     assert L.fwht_float(C.c_void_p(p), 4, 1, 1, 9, None) == _lib.FWHT_E_INVAL
+    # out of place: host-side checks only (nothing reaches a device)
+    q = p + 64 * 4
+    assert L.fwht_float_out(None, C.c_void_p(p), 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_float_out(C.c_void_p(p), None, 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(p + 4), 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL  # misaligned
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(p + 16), 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL  # overlap
+    assert L.fwht_float_out(C.c_void_p(p + 16), C.c_void_p(p), 4, 1, 1, 0, None) == _lib.FWHT_E_INVAL  # overlap
+    assert b"overlap" in L.fwht_last_error()
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 31, 1, 1, 0, None) == _lib.FWHT_E_RANGE
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 4, 0, 1, 0, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 4, 1, 1, 9, None) == _lib.FWHT_E_INVAL
 
 
 def test_threshold_validation(L):

@@ -119,3 +119,39 @@ def test_every_variant_float(F, O, variant, n, spec):
     finally:
         F.set_schedule("float32", n, None)
     assert normwise(y, O.wht_batch(x, n, True)) <= tol(n)
+
+
+@pytest.mark.parametrize("n,batch", [(0, 3), (1, 2), (2, 5), (5, 7), (12, 3), (13, 2), (16, 2), (17, 1), (20, 3),
+                                     (22, 1), (24, 1)])
+@pytest.mark.parametrize("normalize", [True, False])
+def test_float_out_of_place(F, O, n, batch, normalize):
+    """fwht_float_out: the first pass reads src and writes dst; the result must
+    equal the in-place transform bit for bit, src must be untouched, and the
+    result must meet the oracle bound."""
+    import torch
+    x = synth.normal((batch, 1 << n), 700 + 10 * n + batch)
+    src = _dev(x)
+    out = F.fwht_float_out(src, normalize=normalize)
+    ref_t = _dev(x)
+    F.fwht_float_(ref_t, normalize=normalize)
+    torch.cuda.synchronize()
+    assert np.array_equal(src.cpu().numpy(), x)
+    y = out.cpu().numpy()
+    assert np.array_equal(y, ref_t.cpu().numpy())
+    assert normwise(y, O.wht_batch(x, n, normalize)) <= tol(n)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_float_out_of_place_matrix_cores(F, prec):
+    """The matrix-core precisions copy src to dst and transform in place: the
+    same bits as fwht_float_ on a copy."""
+    import torch
+    x = synth.normal((4, 1 << 12), 801)
+    src = _dev(x)
+    out = torch.empty_like(src)
+    F.fwht_float_out(src, out, True, prec)
+    ref_t = _dev(x)
+    F.fwht_float_(ref_t, True, prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(src.cpu().numpy(), x)
+    assert np.array_equal(out.cpu().numpy(), ref_t.cpu().numpy())
