@@ -485,6 +485,11 @@ int fwht_float_out(const float *src, float *dst, int n, int64_t batch, int norma
     hipStream_t s = (hipStream_t)stream;
     if (prec != FWHT_PREC_FP32 || n == 0) {
         // the matrix-core kernels work in place: copy, then transform dst
+        // (their limits checked first, so that a refused call enqueues nothing)
+        if (prec != FWHT_PREC_FP32 && (n < 4 || n > 16))
+            return fail(FWHT_E_UNSUPPORTED, "MFMA precisions need 4 <= n <= 16 (got %d)", n);
+        if (prec != FWHT_PREC_FP32 && (uint64_t)batch > (uint64_t)0x7fffffff)
+            return fail(FWHT_E_RANGE, "batch too large for the MFMA path");
         const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "copy src to dst");
         return fwht_float(dst, n, batch, normalize, prec, stream);

@@ -75,6 +75,9 @@ def test_float_validation(L):
     assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 31, 1, 1, 0, None) == _lib.FWHT_E_RANGE
     assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 4, 0, 1, 0, None) == _lib.FWHT_E_INVAL
     assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 4, 1, 1, 9, None) == _lib.FWHT_E_INVAL
+    # matrix-core limits are checked before the copy is enqueued
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(q), 3, 1, 1, 1, None) == _lib.FWHT_E_UNSUPPORTED
+    assert L.fwht_float_out(C.c_void_p(p), C.c_void_p(p + (1 << 21)), 17, 1, 1, 2, None) == _lib.FWHT_E_UNSUPPORTED
 
 
 def test_threshold_validation(L):
