@@ -84,11 +84,24 @@ __global__ void __launch_bounds__(kOmegaThreads, kOmegaBlocksPerCU * kOmegaThrea
                 const uint64_t f = rr ? (uint64_t)(m.q - rr) : 0ull;  // first multiple of q at or after L
                 const uint64_t j0 = f + (uint64_t)m.c0 * m.q;
                 if (j0 < len) {
-                    // 32-bit walk: j < 2^15 and a step of len or more leaves the segment
+                    // Entry j is the low (j even) or high half of word j / 2.
+                    // Along an even step the half never changes, so each walk
+                    // adds one pre-shifted value over word indices; an odd
+                    // step is walked as two interleaved walks of twice the
+                    // step, one per half.  Steps of len or more leave the
+                    // segment after one add (32-bit walk: j < 2^15).
                     const uint64_t step64 = (uint64_t)m.cs * m.q;
-                    const uint32_t step = step64 < len ? (uint32_t)step64 : len;
-                    for (uint32_t j = (uint32_t)j0; j < len; j += step)
-                        atomicAdd(&seg[j >> 1], m.w << ((j & 1u) * 16u));
+                    const bool odd = step64 & 1u;
+                    const uint64_t st = odd ? 2 * step64 : step64;
+                    const uint32_t wstep = st < len ? (uint32_t)(st >> 1) : words;
+                    const uint64_t j1 = j0 + step64;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint64_t js = h ? j1 : j0;
+                        if (h && (!odd || js >= len)) break;
+                        const uint32_t add = m.w << (((uint32_t)js & 1u) * 16u);
+                        for (uint32_t wi = (uint32_t)js >> 1; wi < words; wi += wstep) atomicAdd(&seg[wi], add);
+                    }
                 }
             }
         }
