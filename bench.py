@@ -305,6 +305,11 @@ def bench_batched(F, torch, np, synth):
     for prec in ("fp16", "bf16"):
         nr = F.norms(x, outs[prec], off, lg, r=ref).cpu().numpy()
         res[prec]["diff_vs_fp32_normwise_max"] = float(f"{np.max(np.sqrt(nr[:, 2] / nr[:, 1])):.3e}")
+    # the FP64 norm reductions themselves (x and y read once; with r, r too)
+    ms_n = _time_replays(torch, lambda: F.norms(x, outs["fp16"], off, lg), 20)
+    ms_nr = _time_replays(torch, lambda: F.norms(x, outs["fp16"], off, lg, r=ref), 20)
+    res["norms"] = {"ms": round(ms_n, 4), "GBs": round(2 * tot * 4 / ms_n / 1e6, 1),
+                    "ms_with_reference": round(ms_nr, 4), "GBs_with_reference": round(4 * tot * 4 / ms_nr / 1e6, 1)}
     res["speedup_fp16_vs_fp32_warm"] = round(res["fp32"]["ms_warm"] / res["fp16"]["ms_warm"], 3)
     res["speedup_fp16_vs_fp32_cold"] = round(res["fp32"]["ms_cold"] / res["fp16"]["ms_cold"], 3)
     del flushbuf, outs, ref, x

@@ -196,7 +196,12 @@ int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, 
  * log2n), writes out[3t] = sum x^2, out[3t+1] = sum y^2 and
  * out[3t+2] = sum (y - r)^2 (0 when r is NULL).  x, y: device FP32; r: device
  * FP64 or NULL; out: device double[3 * count], overwritten.  1 <= count <=
- * 2^23 (FWHT_E_RANGE above). */
+ * 2^23 (FWHT_E_RANGE above).  Each transform is summed in chunks of 2^12
+ * entries whose partial sums are then added in chunk order (the result does
+ * not depend on scheduling); the chunk table of the first call with given
+ * offsets/log2n on a device is kept for later calls with the same arrays (the
+ * four most recent), and only the partial sums are allocated per call, in
+ * stream-ordered memory. */
 int fwht_norms(const float *x, const float *y, const double *r, const int64_t *offsets,
                const int32_t *log2n, int32_t count, double *out, void *stream);
 

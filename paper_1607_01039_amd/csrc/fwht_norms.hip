@@ -2,72 +2,208 @@
 // orthonormal transform keeps the sum of squares, so sum y^2 = sum x^2 up to
 // rounding; with a reference r, sum (y - r)^2 gives the error norm).  These
 // reductions are the only FP64 arithmetic on the GPU.
+//
+// Two launches: every transform is cut into chunks of at most 2^12 entries,
+// one workgroup reduces a chunk to three partial sums (16-byte loads when the
+// chunk is aligned), and one thread per transform then adds its chunks'
+// partials in chunk order, so the result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <list>
+#include <mutex>
 #include <vector>
 
 #include "fwht_internal.hpp"
 
 namespace fwht {
 
-struct NormItem {
-    int64_t off;
-    int64_t len;
+constexpr int kNormThreads = 256;
+constexpr int kNormChunkBits = 12;
+constexpr uint32_t kNormMaxGrid = 1u << 16;  // workgroups of the partial pass; it loops over chunks
+
+struct NormChunk {
+    int64_t off;  // first entry
+    int32_t len;  // entries (<= 2^12)
+    int32_t pad;
 };
 
-__global__ void __launch_bounds__(256) norms_kernel(const float *__restrict__ x, const float *__restrict__ y,
-                                                    const double *__restrict__ r, const NormItem *__restrict__ items,
-                                                    double *__restrict__ out)
+__device__ __forceinline__ void acc(double &s, float v) { s = fma((double)v, (double)v, s); }
+
+__global__ void __launch_bounds__(kNormThreads) norms_partial_kernel(const float *__restrict__ x,
+                                                                     const float *__restrict__ y,
+                                                                     const double *__restrict__ r,
+                                                                     const NormChunk *__restrict__ chunks,
+                                                                     uint32_t nchunks, int vec_ok,
+                                                                     double *__restrict__ part)
 {
-    __shared__ double red[3][256];
-    const NormItem it = items[blockIdx.x];
-    double sx = 0.0, sy = 0.0, se = 0.0;
-    for (int64_t i = threadIdx.x; i < it.len; i += 256) {
-        const double xv = x[it.off + i], yv = y[it.off + i];
-        sx += xv * xv;
-        sy += yv * yv;
-        if (r) {
-            const double d = yv - r[it.off + i];
-            se += d * d;
+    __shared__ double red[3][kNormThreads / 64];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const NormChunk ch = chunks[c];
+        double sx = 0.0, sy = 0.0, se = 0.0;
+        if (vec_ok && ((ch.off | ch.len) & 3) == 0) {
+            // 16-byte loads: four entries of x and y, two 16-byte loads of r
+            const float4 *x4 = reinterpret_cast<const float4 *>(x + ch.off);
+            const float4 *y4 = reinterpret_cast<const float4 *>(y + ch.off);
+            const double2 *r2 = r ? reinterpret_cast<const double2 *>(r + ch.off) : nullptr;
+            for (int32_t i = (int32_t)t; i < ch.len / 4; i += kNormThreads) {
+                const float4 a = x4[i], b = y4[i];
+                acc(sx, a.x), acc(sx, a.y), acc(sx, a.z), acc(sx, a.w);
+                acc(sy, b.x), acc(sy, b.y), acc(sy, b.z), acc(sy, b.w);
+                if (r2) {
+                    const double2 p = r2[2 * i], q = r2[2 * i + 1];
+                    const double d0 = (double)b.x - p.x, d1 = (double)b.y - p.y;
+                    const double d2 = (double)b.z - q.x, d3 = (double)b.w - q.y;
+                    se = fma(d0, d0, se), se = fma(d1, d1, se), se = fma(d2, d2, se), se = fma(d3, d3, se);
+                }
+            }
+        } else {
+            for (int32_t i = (int32_t)t; i < ch.len; i += kNormThreads) {
+                const float a = x[ch.off + i], b = y[ch.off + i];
+                acc(sx, a);
+                acc(sy, b);
+                if (r) {
+                    const double d = (double)b - r[ch.off + i];
+                    se = fma(d, d, se);
+                }
+            }
+        }
+        // wave sums (lane order fixed), then the four waves in order
+        for (int m = 32; m > 0; m >>= 1) {
+            sx += __shfl_xor(sx, m);
+            sy += __shfl_xor(sy, m);
+            se += __shfl_xor(se, m);
+        }
+        if ((t & 63u) == 0) {
+            red[0][t >> 6] = sx;
+            red[1][t >> 6] = sy;
+            red[2][t >> 6] = se;
+        }
+        __syncthreads();
+        if (t < 3) {
+            double s = 0.0;
+            for (int w = 0; w < kNormThreads / 64; ++w) s += red[t][w];
+            part[3 * (uint64_t)c + t] = s;
+        }
+        __syncthreads();  // red is reused by the next chunk
+    }
+}
+
+// out[3t + k] = sum over the chunks of transform t (first[t] .. first[t + 1] - 1) of their partials
+__global__ void __launch_bounds__(kNormThreads) norms_final_kernel(const double *__restrict__ part,
+                                                                   const uint32_t *__restrict__ first,
+                                                                   int32_t count, double *__restrict__ out)
+{
+    const int64_t tr = (int64_t)blockIdx.x * kNormThreads + threadIdx.x;
+    if (tr >= count) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (uint32_t c = first[tr]; c < first[tr + 1]; ++c)
+        for (int k = 0; k < 3; ++k) s[k] += part[3 * (uint64_t)c + k];
+    for (int k = 0; k < 3; ++k) out[3 * tr + k] = s[k];
+}
+
+// The chunk table of a request (the chunks, then first[count + 1]) is built
+// on the host, uploaded once and kept for later calls with the same offsets
+// and sizes on the same device (a few most recent requests); the partial
+// sums are per call, in stream-ordered memory.
+struct NormPlan {
+    int dev = 0;
+    std::vector<int64_t> off;
+    std::vector<int32_t> lg;
+    char *table = nullptr;  // device: NormChunk[nchunks], then uint32 first[count + 1] at foff
+    uint32_t nchunks = 0;
+    size_t foff = 0;
+};
+std::mutex g_norm_mu;
+std::list<NormPlan> g_norm_plans;  // most recent first
+constexpr size_t kMaxNormPlans = 4;
+
+int make_norm_plan(NormPlan &p, const int64_t *offsets, const int32_t *log2n, int32_t count)
+{
+    size_t total = 0;
+    for (int32_t t = 0; t < count; ++t) {
+        if (log2n[t] < 0 || log2n[t] > 30) return fail(FWHT_E_RANGE, "log2n[%d] = %d out of range", t, log2n[t]);
+        if (offsets[t] < 0) return fail(FWHT_E_INVAL, "offsets[%d] < 0", t);
+        total += (((size_t)1 << log2n[t]) + ((size_t)1 << kNormChunkBits) - 1) >> kNormChunkBits;
+    }
+    // chunk indices stay below 2^30, so the grid-stride loop never wraps
+    if (total > ((size_t)1 << 30)) return fail(FWHT_E_RANGE, "too many entries for the norm reductions");
+    std::vector<NormChunk> chunks;
+    chunks.reserve(total);
+    std::vector<uint32_t> first((size_t)count + 1);
+    for (int32_t t = 0; t < count; ++t) {
+        const int64_t len = (int64_t)1 << log2n[t];
+        first[(size_t)t] = (uint32_t)chunks.size();
+        for (int64_t c = 0; c < len; c += (int64_t)1 << kNormChunkBits) {
+            const int64_t l = len - c < ((int64_t)1 << kNormChunkBits) ? len - c : ((int64_t)1 << kNormChunkBits);
+            chunks.push_back(NormChunk{offsets[t] + c, (int32_t)l, 0});
         }
     }
-    red[0][threadIdx.x] = sx;
-    red[1][threadIdx.x] = sy;
-    red[2][threadIdx.x] = se;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) out[3 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+    first[(size_t)count] = (uint32_t)chunks.size();
+    p.nchunks = (uint32_t)chunks.size();
+    const size_t cbytes = sizeof(NormChunk) * chunks.size(), fbytes = sizeof(uint32_t) * first.size();
+    p.foff = (cbytes + 15) & ~(size_t)15;
+    hipError_t e = hipMalloc((void **)&p.table, p.foff + fbytes);
+    if (e != hipSuccess) return fail(FWHT_E_NOMEM, "norms table: %s", hipGetErrorString(e));
+    e = hipMemcpy(p.table, chunks.data(), cbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.table + p.foff, first.data(), fbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "norms table upload");
+    p.off.assign(offsets, offsets + count);
+    p.lg.assign(log2n, log2n + count);
+    return FWHT_OK;
 }
 
 int norms(const float *x, const float *y, const double *r, const int64_t *offsets, const int32_t *log2n,
           int32_t count, double *out, hipStream_t s)
 {
-    std::vector<NormItem> items((size_t)count);
-    for (int32_t t = 0; t < count; ++t) {
-        if (log2n[t] < 0 || log2n[t] > 30) return fail(FWHT_E_RANGE, "log2n[%d] = %d out of range", t, log2n[t]);
-        if (offsets[t] < 0) return fail(FWHT_E_INVAL, "offsets[%d] < 0", t);
-        items[(size_t)t] = NormItem{offsets[t], (int64_t)1 << log2n[t]};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    std::lock_guard<std::mutex> lk(g_norm_mu);
+    auto it = g_norm_plans.begin();
+    for (; it != g_norm_plans.end(); ++it)
+        if (it->dev == dev && it->off.size() == (size_t)count &&
+            !memcmp(it->lg.data(), log2n, sizeof(int32_t) * (size_t)count) &&
+            !memcmp(it->off.data(), offsets, sizeof(int64_t) * (size_t)count))
+            break;
+    if (it == g_norm_plans.end()) {
+        NormPlan p;
+        p.dev = dev;
+        const int rc = make_norm_plan(p, offsets, log2n, count);
+        if (rc) {
+            if (p.table) (void)hipFree(p.table);
+            return rc;
+        }
+        if (g_norm_plans.size() >= kMaxNormPlans) {
+            // an evicted table may still be read by work in flight on some stream
+            (void)hipDeviceSynchronize();
+            if (g_norm_plans.back().table) (void)hipFree(g_norm_plans.back().table);
+            g_norm_plans.pop_back();
+        }
+        g_norm_plans.push_front(std::move(p));
+        it = g_norm_plans.begin();
+    } else if (it != g_norm_plans.begin()) {
+        g_norm_plans.splice(g_norm_plans.begin(), g_norm_plans, it);
+        it = g_norm_plans.begin();
     }
-    // Per-call metadata in stream-ordered memory: allocated, filled, read and
-    // released in the order of `s`, so concurrent calls never share it.
-    const size_t bytes = sizeof(NormItem) * (size_t)count;
-    void *d_items = nullptr;
-    hipError_t e = hipMallocAsync(&d_items, bytes, s);
+    const NormPlan &p = *it;
+    // 16-byte loads need 16-byte aligned bases (chunk offsets are checked per chunk)
+    const int vec_ok = ((((uintptr_t)x) | ((uintptr_t)y) | ((uintptr_t)r)) & 15) == 0;
+    double *part = nullptr;
+    e = hipMallocAsync((void **)&part, sizeof(double) * 3 * (size_t)p.nchunks, s);
     if (e != hipSuccess) return fail(FWHT_E_NOMEM, "norms: %s", hipGetErrorString(e));
-    e = hipMemcpyAsync(d_items, items.data(), bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // `items` is pageable and local
-    if (e != hipSuccess) {
-        (void)hipFreeAsync(d_items, s);
-        return hip_fail(e, "norms upload");
-    }
-    hipLaunchKernelGGL(norms_kernel, dim3((uint32_t)count), dim3(256), 0, s, x, y, r, (const NormItem *)d_items,
-                       out);
+    const uint32_t grid = p.nchunks < kNormMaxGrid ? p.nchunks : kNormMaxGrid;
+    hipLaunchKernelGGL(norms_partial_kernel, dim3(grid), dim3(kNormThreads), 0, s, x, y, r,
+                       (const NormChunk *)p.table, p.nchunks, vec_ok, part);
     e = hipGetLastError();
-    (void)hipFreeAsync(d_items, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(norms_final_kernel, dim3((uint32_t)((count + kNormThreads - 1) / kNormThreads)),
+                           dim3(kNormThreads), 0, s, (const double *)part, (const uint32_t *)(p.table + p.foff),
+                           count, out);
+        e = hipGetLastError();
+    }
+    (void)hipFreeAsync(part, s);
     return e == hipSuccess ? FWHT_OK : hip_fail(e, "norms launch");
 }
 
@@ -78,7 +214,6 @@ extern "C" int fwht_norms(const float *x, const float *y, const double *r, const
 {
     if (!x || !y || !offsets || !log2n || !out) return fwht::fail(FWHT_E_INVAL, "NULL argument");
     if (count < 1) return fwht::fail(FWHT_E_INVAL, "count must be >= 1");
-    // one workgroup of 256 per transform; the dispatch counts work-items in 32 bits
     if (count > (1 << 23)) return fwht::fail(FWHT_E_RANGE, "count must be <= 2^23");
     return fwht::norms(x, y, r, offsets, log2n, count, out, (hipStream_t)stream);
 }

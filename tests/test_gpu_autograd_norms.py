@@ -108,3 +108,25 @@ def test_norms_fp64(F, O):
     assert np.allclose(out[:, 1], out[:, 0], rtol=1e-5)
     out0 = F.norms(xt, yt, off, lg).cpu().numpy()
     assert np.all(out0[:, 2] == 0.0)
+
+
+def test_norms_unaligned_and_large(F, O):
+    """Transforms of 1, 2 and 8 entries at offsets that are not multiples of 4
+    (the scalar path), next to one of 2^22 entries cut into 1024 chunks (the
+    vector path), against the oracle's FP64 sums."""
+    import torch
+    lg = np.array([0, 1, 3, 22, 1, 0, 5], dtype=np.int32)
+    sizes = np.left_shift(np.int64(1), lg.astype(np.int64))
+    off = np.zeros(len(lg), dtype=np.int64)
+    off[1:] = np.cumsum(sizes)[:-1]
+    tot = int(sizes.sum())
+    x = synth.normal(tot, 21)
+    y = synth.normal(tot, 22)
+    r = synth.normal(tot, 23).astype(np.float64)
+    out = F.norms(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), off, lg,
+                  r=torch.from_numpy(r).cuda()).cpu().numpy()
+    sx, sy, se = O.norms(x, y, r, off, lg)
+    assert np.allclose(out[:, 0], sx, rtol=1e-12)
+    assert np.allclose(out[:, 1], sy, rtol=1e-12)
+    assert np.allclose(out[:, 2], se, rtol=1e-12)
+
