@@ -170,7 +170,13 @@ def main():
     torch.cuda.synchronize()
     copy_ms = ce0.elapsed_time(ce1) / 5
     copy_gbs = bytes_per_launch / (copy_ms / 1e3) / 1e9
-    del buf, src
+
+    # the stand-alone threshold pass over the transformed array (one read)
+    F.fwht_int_(buf)
+    hb = F.hit_buffers(buf, 1 << 16)
+    th_ms = _time_replays(torch, lambda: F.threshold(buf, THRESH, hits=hb, sync=False), 10)
+    th_hits = int(hb[2].item())
+    del buf, src, hb
     torch.cuda.empty_cache()
 
     out = {
@@ -195,6 +201,7 @@ def main():
         "pct_hbm_peak_per_pass_avg": round(100 * (len(pass_ms) * bytes_per_launch / (sum(
             float(np.mean(v)) for v in pass_ms.values()) / 1e3) / 1e9) / HBM_PEAK_GBS, 2),
         "copy_kernel_GBs": round(copy_gbs, 1),
+        "threshold_standalone": {"ms": round(th_ms, 4), "GBs_read": round(N * 4 / th_ms / 1e6, 1), "hits": th_hits},
         "planted_mask_recovered": bool(recovered),
         "hits": int(np.median(counts)),
     }

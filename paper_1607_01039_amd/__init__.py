@@ -322,17 +322,26 @@ def fwht_batched_noalloc_(data, offsets, log2n, normalize: bool = True, precisio
     return data
 
 
-def threshold(t, T, cap: int = 1 << 16) -> Hits:
-    """Stand-alone pass: every (k, t[k]) with |t[k]| > T over a 1-D CUDA tensor of 2^n entries."""
+def threshold(t, T, cap: int = 1 << 16, hits=None, sync: bool = True):
+    """Stand-alone pass: every (k, t[k]) with |t[k]| > T over a 1-D CUDA tensor
+    of 2^n entries.  Returns a ``Hits`` after a stream sync when ``sync``, else
+    the (idx, val, count) device buffers; ``hits`` may pass buffers from
+    ``hit_buffers`` (their capacity replaces ``cap``)."""
     torch = _torch()
     dt = {torch.int32: _lib.FWHT_I32, torch.int64: _lib.FWHT_I64, torch.float32: _lib.FWHT_F32}[t.dtype]
     n = _log2(t.numel())
-    idx, val, cnt = _thresh_buffers(t.dtype, cap, t.device)
+    if hits is not None:
+        idx, val, cnt = hits
+        cap = int(idx.numel())
+    else:
+        idx, val, cnt = _thresh_buffers(t.dtype, cap, t.device)
     if dt == _lib.FWHT_F32:
         th = _lib.fwht_thresh_t(0, float(T), idx.data_ptr(), val.data_ptr(), cap, cnt.data_ptr())
     else:
         th = _lib.fwht_thresh_t(int(T), 0.0, idx.data_ptr(), val.data_ptr(), cap, cnt.data_ptr())
     _lib.check(_lib.lib().fwht_threshold(C.c_void_p(t.data_ptr()), dt, n, C.byref(th), _stream_ptr(t)))
+    if not sync:
+        return idx, val, cnt
     torch.cuda.current_stream().synchronize()
     return _collect(idx, val, cnt, cap)
 

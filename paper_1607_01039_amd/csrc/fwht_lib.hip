@@ -343,24 +343,50 @@ int zero_count(uint64_t *count, hipStream_t s)
     return e == hipSuccess ? FWHT_OK : hip_fail(e, "zero count");
 }
 
+// Stand-alone threshold pass: each workgroup takes blocks of 4 x 256
+// 16-byte vectors (a wave's load covers 64 consecutive vectors), issues the
+// four loads before testing any of them, and tests a whole block with one
+// add and compare per entry OR-ed into a lane flag; only a wave with a hit
+// appends, per entry, through the wave-aggregated emission.
 template <class S>
 __global__ void __launch_bounds__(256) threshold_kernel(const S *__restrict__ y, uint64_t len, PassArgs a)
 {
-    constexpr int VEC = 16 / sizeof(S);
+    constexpr int VEC = 16 / sizeof(S), U = 4;
     const HitTest<S> ht(a);
-    const uint64_t stride = (uint64_t)gridDim.x * 256 * VEC;
-    for (uint64_t base = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * VEC; base < len; base += stride) {
-        if (base + VEC <= len) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(y + base);
-            const S *qs = reinterpret_cast<const S *>(&q);
+    const uint32_t t = threadIdx.x;
+    for (uint64_t blk = blockIdx.x;; blk += gridDim.x) {
+        const uint64_t e0 = blk * (256u * U * VEC);  // first entry of the block
+        if (e0 >= len) break;
+        if (e0 + 256u * U * VEC <= len) {
+            uint4 q[U];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) emit_hits<S>(ht.above(qs[e]), base + e, qs[e], a);
+            for (int u = 0; u < U; ++u)
+                q[u] = *reinterpret_cast<const uint4 *>(y + e0 + ((uint64_t)u * 256u + t) * VEC);
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const S *qs = reinterpret_cast<const S *>(&q[u]);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) any |= ht.above(qs[e]);
+            }
+            if (__ballot(any) == 0) continue;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const S *qs = reinterpret_cast<const S *>(&q[u]);
+                const uint64_t k0 = e0 + ((uint64_t)u * 256u + t) * VEC;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) emit_hits<S>(ht.above(qs[e]), k0 + e, qs[e], a);
+            }
         } else {
+            // the last, partial block: entry by entry with bounds
+            for (int u = 0; u < U; ++u) {
+                const uint64_t k0 = e0 + ((uint64_t)u * 256u + t) * VEC;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const bool in = base + e < len;
-                const S x = in ? y[base + e] : S(0);
-                emit_hits<S>(in && ht.above(x), base + e, x, a);
+                for (int e = 0; e < VEC; ++e) {
+                    const bool in = k0 + e < len;
+                    const S x = in ? y[k0 + e] : S(0);
+                    emit_hits<S>(in && ht.above(x), k0 + e, x, a);
+                }
             }
         }
     }
@@ -525,7 +551,7 @@ int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, 
     const uint64_t len = 1ull << n;
     const int esz = dtype == FWHT_I64 ? 8 : 4;
     const uint64_t vecs = (len * esz + 15) / 16;
-    uint64_t grid = (vecs + 255) / 256;
+    uint64_t grid = (vecs + 4 * 256 - 1) / (4 * 256);  // blocks of 4 x 256 vectors
     if (grid > 256 * 16) grid = 256 * 16;
     if (dtype == FWHT_I32)
         hipLaunchKernelGGL(threshold_kernel<uint32_t>, dim3((uint32_t)grid), dim3(256), 0, s, (const uint32_t *)data, len, a);

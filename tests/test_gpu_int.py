@@ -221,22 +221,26 @@ def test_int64_threshold(F, O):
     assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
 
 
+@pytest.mark.parametrize("n", [0, 2, 5, 11, 12, 19])
 @pytest.mark.parametrize("dtype", [np.int32, np.int64, np.float32])
-def test_standalone_threshold(F, O, dtype):
-    n = 19
+def test_standalone_threshold(F, O, dtype, n):
+    """Blocks of 4 x 256 16-byte vectors: n = 19 is whole blocks, n <= 11 only
+    the bounds-checked partial block (one block for int32 at n = 12)."""
     if dtype == np.float32:
         x = synth.normal(1 << n, 3) * 4
         T = 9.5
     else:
         x = synth.ints(1 << n, 3, -1000, 1000, dtype=dtype)
         T = 990
-    x[5] = T
-    x[6] = -T
+    if n >= 3:
+        x[5] = T
+        x[6] = -T
+    x[0] = -2 * T  # a hit in the first entry at every size
     hits = F.threshold(_dev(x), T, cap=1 << 14)
     ridx, rval, rcnt = O.threshold(x, T)
     gi, gv = hits.sorted()
     assert hits.count == rcnt and np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval.astype(dtype))
-    assert 5 not in set(gi.tolist())
+    assert 5 not in set(gi.tolist()) and 0 in set(gi.tolist())
 
 
 def test_repeat_runs_bit_identical(F):
