@@ -171,9 +171,10 @@ def main():
     copy_ms = ce0.elapsed_time(ce1) / 5
     copy_gbs = bytes_per_launch / (copy_ms / 1e3) / 1e9
 
-    # the stand-alone threshold pass over the transformed array (one read)
-    F.fwht_int_(buf)
+    # the stand-alone threshold pass over the transformed array (one read); the
+    # transform is the benchmark's own call, so every pass kernel keeps one name
     hb = F.hit_buffers(buf, 1 << 16)
+    F.fwht_int_(buf, threshold=THRESH, hits=hb)
     th_ms = _time_replays(torch, lambda: F.threshold(buf, THRESH, hits=hb, sync=False), 10)
     th_hits = int(hb[2].item())
     del buf, src, hb
