@@ -223,6 +223,10 @@ int make_plan(Plan &p, const int64_t *off, const int32_t *lg, int32_t count, int
 int capture_graph(Plan &p)
 {
     hipError_t e = hipSuccess;
+    if (p.graph) {  // left by an earlier capture that failed to instantiate
+        (void)hipGraphDestroy(p.graph);
+        p.graph = nullptr;
+    }
     if (!g_capture) {
         e = hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "capture stream");
