@@ -183,26 +183,27 @@ DEFINE_FIG1(wht_fig1_f64, stage_f64, double)
 /* Fig. 2: ParallelWHT(buf, 2^n, m), m = 2^q cores, fork-join phases  */
 /* ------------------------------------------------------------------ */
 
-/* workload(buf0, pt0, j0): `count` consecutive butterflies at distance j0
- * starting at pt0 (the subtask of Fig. 2; there count = 2^(n-3) for m=4). */
+/* One Fig. 2 subtask of a late stage: `count` butterflies of that stage over
+ * the consecutive lower indices first .. first + count - 1, each paired with
+ * the index `dist` above it (for m = 4 a subtask holds 2^(n-3) of them). */
 #define WORKLOAD_BODY(T)                                                    \
     {                                                                       \
-        uint64_t pt = pt0;                                                  \
         for (uint64_t i = 0; i < count; i++) {                              \
-            T a = buf[pt], b = buf[pt + j0];                                \
-            buf[pt] = a + b; buf[pt + j0] = a - b;                          \
-            pt++;                                                           \
+            const uint64_t lo = first + i, hi = lo + dist;                  \
+            T a = buf[lo], b = buf[hi];                                     \
+            buf[lo] = a + b;                                                \
+            buf[hi] = a - b;                                                \
         }                                                                   \
     }
-static void workload_u32(uint32_t *buf, uint64_t pt0, uint64_t j0, uint64_t count) WORKLOAD_BODY(uint32_t)
-static void workload_u64(uint64_t *buf, uint64_t pt0, uint64_t j0, uint64_t count) WORKLOAD_BODY(uint64_t)
+static void workload_u32(uint32_t *buf, uint64_t first, uint64_t dist, uint64_t count) WORKLOAD_BODY(uint32_t)
+static void workload_u64(uint64_t *buf, uint64_t first, uint64_t dist, uint64_t count) WORKLOAD_BODY(uint64_t)
 
 typedef struct {
     void *buf;
     int elem; /* 4 or 8 */
     int phase; /* 0: WHT of a quarter-style block; 1: workload */
     int nsub;  /* log2 of the block size for phase 0 */
-    uint64_t pt0, j0, count;
+    uint64_t first, dist, count;
 } subtask_t;
 
 static void *run_subtask(void *p)
@@ -212,8 +213,8 @@ static void *run_subtask(void *p)
         if (s->elem == 4) wht_fig1_u32((uint32_t *)s->buf, s->nsub);
         else              wht_fig1_u64((uint64_t *)s->buf, s->nsub);
     } else {
-        if (s->elem == 4) workload_u32((uint32_t *)s->buf, s->pt0, s->j0, s->count);
-        else              workload_u64((uint64_t *)s->buf, s->pt0, s->j0, s->count);
+        if (s->elem == 4) workload_u32((uint32_t *)s->buf, s->first, s->dist, s->count);
+        else              workload_u64((uint64_t *)s->buf, s->first, s->dist, s->count);
     }
     return NULL;
 }
@@ -255,8 +256,8 @@ static int fig2(void *buf, int elem, int n, int q)
 #endif
             t[r].buf = buf;
             t[r].phase = 1;
-            t[r].pt0 = start;
-            t[r].j0 = 1ULL << k;
+            t[r].first = start;
+            t[r].dist = 1ULL << k;
             t[r].count = L;
         }
         fork_join(t, m);
