@@ -196,7 +196,10 @@ int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, 
  * log2n), writes out[3t] = sum x^2, out[3t+1] = sum y^2 and
  * out[3t+2] = sum (y - r)^2 (0 when r is NULL).  x, y: device FP32; r: device
  * FP64 or NULL; out: device double[3 * count], overwritten.  1 <= count <=
- * 2^23 (FWHT_E_RANGE above).  Each transform is summed in chunks of 2^12
+ * 2^23 (FWHT_E_RANGE above); each log2n[t] in [0, 30] (FWHT_E_RANGE) and
+ * offsets[t] >= 0 (FWHT_E_INVAL); at most 2^30 chunks in all (FWHT_E_RANGE;
+ * chunks are defined below, a transform smaller than one is one chunk).
+ * Each transform is summed in chunks of 2^12
  * entries whose partial sums are then added in chunk order (the result does
  * not depend on scheduling); the chunk table of the first call with given
  * offsets/log2n on a device is kept for later calls with the same arrays (the

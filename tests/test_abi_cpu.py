@@ -247,3 +247,18 @@ def test_batched_launch_mode_switch(L):
     assert L.fwht_set_batched_graphs(1) == 0 and L.fwht_get_batched_graphs() == 1
     assert L.fwht_set_batched_graphs(7) == 0 and L.fwht_get_batched_graphs() == 1
     assert L.fwht_set_batched_graphs(0) == 0 and L.fwht_get_batched_graphs() == 0
+
+
+def test_norms_validation(L):
+    """Argument checks of fwht_norms that come before any device call."""
+    from paper_1607_01039_amd import _lib
+    keep, p = _buf()
+    off = (C.c_int64 * 1)(0)
+    lg = (C.c_int32 * 1)(4)
+    v = C.c_void_p(p)
+    for args in ((None, v, None, off, lg, 1, v), (v, None, None, off, lg, 1, v), (v, v, None, None, lg, 1, v),
+                 (v, v, None, off, None, 1, v), (v, v, None, off, lg, 1, None)):
+        assert L.fwht_norms(*args, None) == _lib.FWHT_E_INVAL
+    assert b"NULL" in L.fwht_last_error()
+    assert L.fwht_norms(v, v, None, off, lg, 0, v, None) == _lib.FWHT_E_INVAL
+    assert L.fwht_norms(v, v, None, off, lg, (1 << 23) + 1, v, None) == _lib.FWHT_E_RANGE
