@@ -47,7 +47,33 @@ __global__ void __launch_bounds__(kNormThreads) norms_partial_kernel(const float
             const float4 *x4 = reinterpret_cast<const float4 *>(x + ch.off);
             const float4 *y4 = reinterpret_cast<const float4 *>(y + ch.off);
             const double2 *r2 = r ? reinterpret_cast<const double2 *>(r + ch.off) : nullptr;
-            for (int32_t i = (int32_t)t; i < ch.len / 4; i += kNormThreads) {
+            const int32_t nv = ch.len / 4;
+            int32_t i = (int32_t)t;
+            // four of this thread's vectors per round, every load issued
+            // before the first is used; the sums take them in the same order
+            for (; i + 3 * kNormThreads < nv; i += 4 * kNormThreads) {
+                float4 a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = x4[i + u * kNormThreads], b[u] = y4[i + u * kNormThreads];
+                if (r2) {
+                    double2 p[4], q[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        p[u] = r2[2 * (i + u * kNormThreads)], q[u] = r2[2 * (i + u * kNormThreads) + 1];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double d0 = (double)b[u].x - p[u].x, d1 = (double)b[u].y - p[u].y;
+                        const double d2 = (double)b[u].z - q[u].x, d3 = (double)b[u].w - q[u].y;
+                        se = fma(d0, d0, se), se = fma(d1, d1, se), se = fma(d2, d2, se), se = fma(d3, d3, se);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc(sx, a[u].x), acc(sx, a[u].y), acc(sx, a[u].z), acc(sx, a[u].w);
+                    acc(sy, b[u].x), acc(sy, b[u].y), acc(sy, b[u].z), acc(sy, b[u].w);
+                }
+            }
+            for (; i < nv; i += kNormThreads) {
                 const float4 a = x4[i], b = y4[i];
                 acc(sx, a.x), acc(sx, a.y), acc(sx, a.z), acc(sx, a.w);
                 acc(sy, b.x), acc(sy, b.y), acc(sy, b.z), acc(sy, b.w);
@@ -98,7 +124,18 @@ __global__ void __launch_bounds__(kNormThreads) norms_final_kernel(const double 
     const int64_t tr = (int64_t)blockIdx.x * kNormThreads + threadIdx.x;
     if (tr >= count) return;
     double s[3] = {0.0, 0.0, 0.0};
-    for (uint32_t c = first[tr]; c < first[tr + 1]; ++c)
+    const uint32_t c1 = first[tr + 1];
+    uint32_t c = first[tr];
+    // four chunks' partials loaded before they are added, in chunk order
+    for (; c + 4 <= c1; c += 4) {
+        double q[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) q[u] = part[3 * (uint64_t)c + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            for (int k = 0; k < 3; ++k) s[k] += q[3 * u + k];
+    }
+    for (; c < c1; ++c)
         for (int k = 0; k < 3; ++k) s[k] += part[3 * (uint64_t)c + k];
     for (int k = 0; k < 3; ++k) out[3 * tr + k] = s[k];
 }
