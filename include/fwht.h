@@ -201,10 +201,12 @@ int fwht_threshold(const void *data, int dtype, int n, const fwht_thresh_t *th, 
  * chunks are defined below, a transform smaller than one is one chunk).
  * Each transform is summed in chunks of 2^12
  * entries whose partial sums are then added in chunk order (the result does
- * not depend on scheduling); the chunk table of the first call with given
- * offsets/log2n on a device is kept for later calls with the same arrays (the
- * four most recent), and only the partial sums are allocated per call, in
- * stream-ordered memory. */
+ * not depend on scheduling); the chunk table and a buffer of partial sums
+ * are allocated on the first call with given offsets/log2n on a device and
+ * kept for later calls with the same arrays (the four most recent).  Calls
+ * of one request share that buffer, so each waits on the GPU for the
+ * previous one (an event recorded after its last kernel): calls on different
+ * streams are ordered, not overlapped. */
 int fwht_norms(const float *x, const float *y, const double *r, const int64_t *offsets,
                const int32_t *log2n, int32_t count, double *out, void *stream);
 

@@ -352,10 +352,9 @@ def norms(x, y, offsets, log2n, r=None):
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     lg = np.ascontiguousarray(np.asarray(log2n, dtype=np.int32))
     out = torch.empty((len(off), 3), dtype=torch.float64, device=x.device)
-    _lib.check(_lib.lib().fwht_norms(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
-                                     C.c_void_p(r.data_ptr()) if r is not None else None,
-                                     off.ctypes.data_as(C.c_void_p), lg.ctypes.data_as(C.c_void_p),
-                                     len(off), C.c_void_p(out.data_ptr()), _stream_ptr(x)))
+    # raw addresses: ctypes converts the ints itself, faster than explicit casts
+    _lib.check(_lib.lib().fwht_norms(x.data_ptr(), y.data_ptr(), r.data_ptr() if r is not None else None,
+                                     off.ctypes.data, lg.ctypes.data, len(off), out.data_ptr(), _stream_ptr(x)))
     return out
 
 

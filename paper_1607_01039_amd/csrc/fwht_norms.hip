@@ -142,16 +142,32 @@ __global__ void __launch_bounds__(kNormThreads) norms_final_kernel(const double 
 
 // The chunk table of a request (the chunks, then first[count + 1]) is built
 // on the host, uploaded once and kept for later calls with the same offsets
-// and sizes on the same device (a few most recent requests); the partial
-// sums are per call, in stream-ordered memory.
+// and sizes on the same device (a few most recent requests), together with
+// the buffer of partial sums that those calls share.  A call records an event
+// after its last kernel and the next call of the same request, on whatever
+// stream, waits for it, so no call overwrites partial sums another is still
+// adding.
 struct NormPlan {
     int dev = 0;
     std::vector<int64_t> off;
     std::vector<int32_t> lg;
     char *table = nullptr;  // device: NormChunk[nchunks], then uint32 first[count + 1] at foff
+    double *part = nullptr;  // device: 3 partial sums per chunk
+    hipEvent_t done = nullptr;  // recorded after the last call's final kernel
+    bool used = false;
     uint32_t nchunks = 0;
     size_t foff = 0;
 };
+
+void release(NormPlan &p)
+{
+    if (p.table) (void)hipFree(p.table);
+    if (p.part) (void)hipFree(p.part);
+    if (p.done) (void)hipEventDestroy(p.done);
+    p.table = nullptr;
+    p.part = nullptr;
+    p.done = nullptr;
+}
 std::mutex g_norm_mu;
 std::list<NormPlan> g_norm_plans;  // most recent first
 constexpr size_t kMaxNormPlans = 4;
@@ -182,7 +198,10 @@ int make_norm_plan(NormPlan &p, const int64_t *offsets, const int32_t *log2n, in
     const size_t cbytes = sizeof(NormChunk) * chunks.size(), fbytes = sizeof(uint32_t) * first.size();
     p.foff = (cbytes + 15) & ~(size_t)15;
     hipError_t e = hipMalloc((void **)&p.table, p.foff + fbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&p.part, sizeof(double) * 3 * chunks.size());
     if (e != hipSuccess) return fail(FWHT_E_NOMEM, "norms table: %s", hipGetErrorString(e));
+    e = hipEventCreateWithFlags(&p.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "norms event");
     e = hipMemcpy(p.table, chunks.data(), cbytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p.table + p.foff, first.data(), fbytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "norms table upload");
@@ -209,13 +228,13 @@ int norms(const float *x, const float *y, const double *r, const int64_t *offset
         p.dev = dev;
         const int rc = make_norm_plan(p, offsets, log2n, count);
         if (rc) {
-            if (p.table) (void)hipFree(p.table);
+            release(p);
             return rc;
         }
         if (g_norm_plans.size() >= kMaxNormPlans) {
-            // an evicted table may still be read by work in flight on some stream
+            // an evicted plan may still be used by work in flight on some stream
             (void)hipDeviceSynchronize();
-            if (g_norm_plans.back().table) (void)hipFree(g_norm_plans.back().table);
+            release(g_norm_plans.back());
             g_norm_plans.pop_back();
         }
         g_norm_plans.push_front(std::move(p));
@@ -224,24 +243,27 @@ int norms(const float *x, const float *y, const double *r, const int64_t *offset
         g_norm_plans.splice(g_norm_plans.begin(), g_norm_plans, it);
         it = g_norm_plans.begin();
     }
-    const NormPlan &p = *it;
+    NormPlan &p = *it;
     // 16-byte loads need 16-byte aligned bases (chunk offsets are checked per chunk)
     const int vec_ok = ((((uintptr_t)x) | ((uintptr_t)y) | ((uintptr_t)r)) & 15) == 0;
-    double *part = nullptr;
-    e = hipMallocAsync((void **)&part, sizeof(double) * 3 * (size_t)p.nchunks, s);
-    if (e != hipSuccess) return fail(FWHT_E_NOMEM, "norms: %s", hipGetErrorString(e));
+    if (p.used) {
+        e = hipStreamWaitEvent(s, p.done, 0);
+        if (e != hipSuccess) return hip_fail(e, "norms: wait for the previous call");
+    }
     const uint32_t grid = p.nchunks < kNormMaxGrid ? p.nchunks : kNormMaxGrid;
     hipLaunchKernelGGL(norms_partial_kernel, dim3(grid), dim3(kNormThreads), 0, s, x, y, r,
-                       (const NormChunk *)p.table, p.nchunks, vec_ok, part);
+                       (const NormChunk *)p.table, p.nchunks, vec_ok, p.part);
     e = hipGetLastError();
     if (e == hipSuccess) {
         hipLaunchKernelGGL(norms_final_kernel, dim3((uint32_t)((count + kNormThreads - 1) / kNormThreads)),
-                           dim3(kNormThreads), 0, s, (const double *)part, (const uint32_t *)(p.table + p.foff),
-                           count, out);
+                           dim3(kNormThreads), 0, s, (const double *)p.part,
+                           (const uint32_t *)(p.table + p.foff), count, out);
         e = hipGetLastError();
     }
-    (void)hipFreeAsync(part, s);
-    return e == hipSuccess ? FWHT_OK : hip_fail(e, "norms launch");
+    if (e == hipSuccess) e = hipEventRecord(p.done, s);
+    if (e != hipSuccess) return hip_fail(e, "norms launch");
+    p.used = true;
+    return FWHT_OK;
 }
 
 }  // namespace fwht

@@ -130,3 +130,30 @@ def test_norms_unaligned_and_large(F, O):
     assert np.allclose(out[:, 1], sy, rtol=1e-12)
     assert np.allclose(out[:, 2], se, rtol=1e-12)
 
+
+
+def test_norms_same_request_two_streams(F, O):
+    """Calls of one request share its buffer of partial sums: back-to-back calls
+    on two streams, each with inputs of its own and an FP64 reference, must both
+    match the oracle (the second waits on the GPU for the first)."""
+    import torch
+    lg, off, tot = synth.ragged(64, 8, 16, 12)
+    xs = [synth.normal(tot, 31 + k) for k in range(3)]
+    ys = [synth.normal(tot, 41 + k) for k in range(3)]
+    rs = [synth.normal(tot, 51 + k).astype(np.float64) for k in range(3)]
+    xt = [torch.from_numpy(a).cuda() for a in xs]
+    yt = [torch.from_numpy(a).cuda() for a in ys]
+    rt = [torch.from_numpy(a).cuda() for a in rs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream()]
+    torch.cuda.synchronize()
+    outs = []
+    for k, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            outs.append(F.norms(xt[k], yt[k], off, lg, r=rt[k]))
+    torch.cuda.synchronize()
+    for k in range(3):
+        sx, sy, se = O.norms(xs[k], ys[k], rs[k], off, lg)
+        got = outs[k].cpu().numpy()
+        assert np.allclose(got[:, 0], sx, rtol=1e-12)
+        assert np.allclose(got[:, 1], sy, rtol=1e-12)
+        assert np.allclose(got[:, 2], se, rtol=1e-12)
