@@ -43,9 +43,11 @@ NT_MIN_TB = {"int32": 13, "float32": 13, "int64": 12}
 WHOLE_FIRST = {"int32": {16: ("C16", "C16n"), 15: ("C15p", "C15pn")},
                "float32": {16: ("C16", "C16n"), 15: ("C15p", "C15pn")},
                "int64": {14: ("C14p", "C14pn")}}
-# strided variants held in registers by 512 threads, two workgroups per CU
-# (8-byte types): (column bits, row bits) -> name
-HELD = {"int64": {(6, 8): "S14c6p"}}
+# strided variants held in registers by 512 threads, two workgroups per CU:
+# (column bits, row bits) -> name
+HELD = {"int64": {(6, 8): "S14c6p"},
+        "int32": {(7, 8): "S15c7p", (8, 7): "S15c8p"},
+        "float32": {(7, 8): "S15c7p", (8, 7): "S15c8p"}}
 
 
 # row-segment widths compiled for the tile variants of up to 2^15 entries

@@ -22,6 +22,9 @@ std::vector<Variant> variants_u32()
         Variant{"S16c7", 16, 7, 1024, false, &launch_pinned16<S, 7, 0>, true},
         Variant{"S16c8", 16, 8, 1024, false, &launch_pinned16<S, 8, 0>, true},
         Variant{"S16c9", 16, 9, 1024, false, &launch_pinned16<S, 9, 0>, true},
+        // 2^15-entry strided tiles held by 512 threads (two workgroups per CU), full height only
+        Variant{"S15c7p", 15, 7, 512, false, &launch_strided15p<S, 7>, true},
+        Variant{"S15c8p", 15, 8, 512, false, &launch_strided15p<S, 8>, true},
         Variant{"S8c5", 8, 5, 64, false, &launch_tile<8, 5, 64, false, S, false>},
         Variant{"S9c5", 9, 5, 64, false, &launch_tile<9, 5, 64, false, S, false>},
         Variant{"S10c5", 10, 5, 64, false, &launch_tile<10, 5, 64, false, S, false>},
@@ -58,6 +61,8 @@ std::vector<Variant> variants_u32()
         Variant{"S16c7n", 16, 7, 1024, false, &launch_pinned16<S, 7, NT_LOAD | NT_STORE>, true},
         Variant{"S16c8n", 16, 8, 1024, false, &launch_pinned16<S, 8, NT_LOAD | NT_STORE>, true},
         Variant{"S16c9n", 16, 9, 1024, false, &launch_pinned16<S, 9, NT_LOAD | NT_STORE>, true},
+        Variant{"S15c7pn", 15, 7, 512, false, &launch_strided15p<S, 7, NT_LOAD | NT_STORE>, true},
+        Variant{"S15c8pn", 15, 8, 512, false, &launch_strided15p<S, 8, NT_LOAD | NT_STORE>, true},
         Variant{"S13c5n", 13, 5, 512, false, &launch_tile<13, 5, 512, false, S, NT_LOAD | NT_STORE>},
         Variant{"S14c5n", 14, 5, 512, false, &launch_tile<14, 5, 512, false, S, NT_LOAD | NT_STORE>},
         Variant{"S13c6n", 13, 6, 512, false, &launch_tile<13, 6, 512, false, S, NT_LOAD | NT_STORE>},

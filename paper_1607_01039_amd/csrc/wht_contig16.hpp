@@ -265,5 +265,14 @@ hipError_t launch_strided14p(void *buf, const PassArgs &a, hipStream_t s)
     static_assert(sizeof(S) == 8, "8-byte entries");
     return launch_pinned16<S, CB, NTM, 14, 512>(buf, a, s);
 }
+// The strided 4-byte counterparts "S15c7p" and "S15c8p": 2^8 rows x 512 B and
+// 2^7 rows x 1 KiB, half-tile transposes through 66 KiB of LDS, two
+// workgroups per CU.
+template <class S, int CB, int NTM = 0>
+hipError_t launch_strided15p(void *buf, const PassArgs &a, hipStream_t s)
+{
+    static_assert(sizeof(S) == 4, "4-byte entries");
+    return launch_pinned16<S, CB, NTM, 15, 512>(buf, a, s);
+}
 
 }  // namespace fwht

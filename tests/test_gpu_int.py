@@ -170,6 +170,40 @@ def test_fused_threshold_matches_oracle(F, O, n, p, seed, T):
         assert s in set(gi.tolist())
 
 
+def _register_strided_int32():
+    import paper_1607_01039_amd as F
+    try:
+        names = F.list_variants("int32")
+    except Exception:  # library not built: the test itself will fail loudly
+        return ["unbuilt"]
+    return [v for v in names if v.startswith("S16") or (v.startswith("S") and v.rstrip("n").endswith("p"))]
+
+
+@pytest.mark.parametrize("variant", _register_strided_int32())
+def test_fused_threshold_register_strided(F, O, variant):
+    """The threshold fused into a register-resident strided pass (2^16-entry
+    tiles in 1024 threads, 2^15-entry tiles in 512) as the last pass: every
+    entry, the hit set and the hit values against the oracle."""
+    core = variant[:-1] if variant.endswith("n") else variant
+    tb, cb = (int(x) for x in core[1:].rstrip("p").split("c"))
+    R = tb - cb
+    n = 12 + R
+    x, s, err = synth.planted(n, 70 + n, 0.4)
+    T = 4 << (n // 2)
+    F.set_schedule("int32", n, f"C12,{variant}:{R}")
+    try:
+        y, hits = _run_int(F, x, threshold=T, cap=1 << n)
+    finally:
+        F.set_schedule("int32", n, None)
+    ref = O.wht_fig1(x)
+    assert np.array_equal(y, ref)
+    ridx, rval, rcnt = O.threshold(ref, T)
+    assert rcnt > 1 and hits.count == rcnt
+    gi, gv = hits.sorted()
+    assert np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+    assert s in set(gi.tolist())
+
+
 @pytest.mark.parametrize("n", [12, 20, 30])
 def test_reused_hit_buffers(F, O, n):
     """The library clears the hit count itself (inside the first of several
