@@ -262,3 +262,26 @@ def test_norms_validation(L):
     assert b"NULL" in L.fwht_last_error()
     assert L.fwht_norms(v, v, None, off, lg, 0, v, None) == _lib.FWHT_E_INVAL
     assert L.fwht_norms(v, v, None, off, lg, (1 << 23) + 1, v, None) == _lib.FWHT_E_RANGE
+
+
+def test_autotuner_candidates_parse(L):
+    """Every schedule the autotuner would time names compiled variants at
+    heights the library accepts, including the held (two workgroups per CU)
+    strided tiles; the held strided variants it knows are exactly the
+    compiled ones."""
+    import paper_1607_01039_amd as F
+    from paper_1607_01039_amd import autotune as A
+    codes = {"int32": 0, "int64": 1, "float32": 2}
+    for dt, code in codes.items():
+        names = set(F.list_variants(dt))
+        held = {v for v in names if v.startswith("S") and v.rstrip("n").endswith("p")}
+        assert {v for v in A.HELD.get(dt, {}).values()} | {v + "n" for v in A.HELD.get(dt, {}).values()} == held
+        for n in (20, 24, 28, 30):
+            cands = A.candidates(dt, n)
+            assert cands
+            for spec in cands:
+                for part in spec.split(","):
+                    assert part.split(":")[0] in names, (dt, n, spec)
+                rc = L.fwht_set_schedule(code, n, spec.encode())
+                assert rc == 0, (dt, n, spec, L.fwht_last_error())
+            assert L.fwht_set_schedule(code, n, None) == 0
