@@ -80,7 +80,7 @@ typedef struct {
  * stages of Fig. 1 regrouped into HBM passes).
  *   data  : 2^n int32 (dtype FWHT_I32, n <= 30) or int64 (FWHT_I64) entries,
  *           16-byte aligned.  A device pointer selects the in-HBM path
- *           (n <= 34, asynchronous).  A pinned host pointer selects the
+ *           (n <= 35, asynchronous).  A pinned host pointer selects the
  *           streamed Kronecker path (10 <= n, at most 2^35 bytes, i.e.
  *           n <= 32 for int64): the array is split as
  *           H_{2^(n-L)} (x) H_{2^L}, L = ceil(n/2), and both factors are

@@ -459,7 +459,8 @@ int fwht_int(void *data, int dtype, int n, const fwht_thresh_t *th, void *stream
         if (th && th->cap > 0 && (!th->idx || !th->val)) return fail(FWHT_E_INVAL, "threshold: idx/val NULL");
         return streamed_int(data, dtype, n, th, s);
     }
-    if (n > 34) return fail(FWHT_E_RANGE, "in-HBM transforms are limited to n <= 34");
+    // 2^35 int64 entries (256 GiB) still fit one GPU's 288 GB of HBM
+    if (n > 35) return fail(FWHT_E_RANGE, "in-HBM transforms are limited to n <= 35");
     Epilogue epi{};
     if (th) {
         epi.thresh = 1;

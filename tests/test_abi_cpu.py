@@ -110,7 +110,7 @@ def test_schedule_parsing(L):
 
 
 def test_default_schedules_cover_every_n(L):
-    for dt, nmax in ((0, 30), (1, 34), (2, 30)):
+    for dt, nmax in ((0, 30), (1, 35), (2, 30)):
         for n in range(1, nmax + 1):
             buf = C.create_string_buffer(128)
             assert L.fwht_get_schedule(dt, n, buf, 128) == 0
