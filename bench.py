@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--streamed", type=int, default=0, metavar="N",
                     help="instead of the default workload, time the streamed path on an int64 planted "
                          "signal of 2^N entries held in pinned host memory (10 <= N <= 32)")
+    ap.add_argument("--in-hbm", type=int, default=0, metavar="N",
+                    help="instead of the default workload, time the in-place int64 transform of a planted "
+                         "signal of 2^N entries resident in HBM (N <= 35; 2^35 entries are 256 GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -101,6 +104,9 @@ def main():
 
     if args.streamed:
         print(json.dumps(bench_streamed(F, torch, np, synth, args.streamed)), flush=True)
+        return
+    if args.in_hbm:
+        print(json.dumps(bench_in_hbm(F, torch, np, synth, args.in_hbm)), flush=True)
         return
 
     n = args.n
@@ -402,6 +408,49 @@ def bench_streamed(F, torch, np, synth, n):
             "bytes_over_link": link_bytes, "link_GBs_effective": round(link_bytes / sec / 1e9, 2),
             "pinned_copy_GBs": rates, "link_frac_of_bidirectional": round(link_bytes / sec / 1e9 / rates["both"], 3),
             "threshold": T, "hits": hits.count, "planted_mask_recovered": bool(ok)}
+
+
+def bench_in_hbm(F, torch, np, synth, n):
+    """Planted int64 signal of 2^n entries (seed 3, p = 0.48, the streamed
+    workload's generator) written into HBM chunk by chunk from one pinned host
+    chunk, then transformed in place with the threshold T = ceil(6 * 2^(n/2))
+    fused: wall time of the (synchronised) call, per-pass device times and the
+    recovery checks."""
+    import math
+    N = 1 << n
+    T = int(math.ceil(6 * 2 ** (n / 2)))
+    ch = min(N, 1 << 27)
+    log(f"[bench] in-HBM int64 n={n}: {N * 8 / 2**30:.0f} GiB on the device")
+    t = torch.empty(N, dtype=torch.int64, device="cuda")
+    host = torch.empty(ch, dtype=torch.int64, pin_memory=True)
+    err, s = 0, None
+    for c0 in range(0, N, ch):
+        _, s, e = synth.planted(n, 3, 0.48, dtype=np.int64, start=c0, count=ch, out=host.numpy())
+        t[c0:c0 + ch].copy_(host)
+        err += e
+        if (c0 // ch) % 64 == 63:
+            log(f"[bench] in-HBM: generated {(c0 + ch) / N:.0%}")
+    del host
+    hb = F.hit_buffers(t, 1 << 12)
+    F.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fwht_int_(t, threshold=T, sync=False, hits=hb)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    passes = [{"pass": nm, "ms": round(ms, 2), "GBs": round(2 * N * 8 / (ms / 1e3) / 1e9, 1)}
+              for nm, ms in F.trace_read()]
+    F.trace_enable(False)
+    hits = F._collect(*hb, 1 << 12)
+    gi, gv = hits.sorted()
+    ok = s in set(gi.tolist()) and int(gv[list(gi).index(s)]) == N - 2 * err
+    log(f"[bench] in-HBM: {sec:.3f} s, {hits.count} hits")
+    del t, hb
+    torch.cuda.empty_cache()
+    return {"metric": "in-HBM FWHT GElem/s (int64, fused |W|>T extraction)",
+            "value": round(N / sec / 1e9, 2), "unit": "GElem/s", "seconds": round(sec, 4), "n": n,
+            "schedule": F.get_schedule("int64", n), "passes": passes, "threshold": T, "hits": hits.count,
+            "planted_mask_recovered": bool(ok)}
 
 
 def bench_autograd(F, torch, np, synth):
