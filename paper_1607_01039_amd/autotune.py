@@ -48,6 +48,9 @@ WHOLE_FIRST = {"int32": {16: ("C16", "C16n"), 15: ("C15p", "C15pn")},
 HELD = {"int64": {(6, 8): "S14c6p"},
         "int32": {(7, 8): "S15c7p", (8, 7): "S15c8p"},
         "float32": {(7, 8): "S15c7p", (8, 7): "S15c8p"}}
+# 8-byte strided tiles of 2^14 entries also held by 1024 threads (16 entries
+# each instead of 32): (column bits, row bits) -> name
+WIDE = {"int64": {(5, 9): "S14c5w", (6, 8): "S14c6w", (7, 7): "S14c7w"}}
 
 
 # row-segment widths compiled for the tile variants of up to 2^15 entries
@@ -69,8 +72,9 @@ def strided_variants(dtype: str, r: int, cb: int):
     if (1 << tb) // nt < vec:
         return []
     out = [f"S{tb}c{cb}"]
-    if (cb, r) in HELD.get(dtype, {}):
-        out.append(HELD[dtype][(cb, r)])
+    for extra in (HELD, WIDE):
+        if (cb, r) in extra.get(dtype, {}):
+            out.append(extra[dtype][(cb, r)])
     return out
 
 

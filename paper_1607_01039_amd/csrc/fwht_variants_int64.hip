@@ -57,6 +57,10 @@ std::vector<Variant> variants_u64()
         Variant{"S12c7", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, false>},
         Variant{"S13c7", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, false>},
         Variant{"S14c7", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, false>},
+        // the 2^14-entry tiles held by 1024 threads (16 entries each, twice the waves per CU)
+        Variant{"S14c5w", 14, 5, 1024, false, &launch_tile<14, 5, 1024, false, S, false>},
+        Variant{"S14c6w", 14, 6, 1024, false, &launch_tile<14, 6, 1024, false, S, false>},
+        Variant{"S14c7w", 14, 7, 1024, false, &launch_tile<14, 7, 1024, false, S, false>},
         // twins with non-temporal loads and stores (the autotuner picks per size)
         Variant{"S12c4n", 12, 4, 256, false, &launch_tile<12, 4, 256, false, S, NT_LOAD | NT_STORE>},
         Variant{"S13c4n", 13, 4, 512, false, &launch_tile<13, 4, 512, false, S, NT_LOAD | NT_STORE>},
@@ -69,6 +73,9 @@ std::vector<Variant> variants_u64()
         Variant{"S12c7n", 12, 7, 256, false, &launch_tile<12, 7, 256, false, S, NT_LOAD | NT_STORE>},
         Variant{"S13c7n", 13, 7, 512, false, &launch_tile<13, 7, 512, false, S, NT_LOAD | NT_STORE>},
         Variant{"S14c7n", 14, 7, 512, false, &launch_tile<14, 7, 512, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c5wn", 14, 5, 1024, false, &launch_tile<14, 5, 1024, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c6wn", 14, 6, 1024, false, &launch_tile<14, 6, 1024, false, S, NT_LOAD | NT_STORE>},
+        Variant{"S14c7wn", 14, 7, 1024, false, &launch_tile<14, 7, 1024, false, S, NT_LOAD | NT_STORE>},
     };
 }
 

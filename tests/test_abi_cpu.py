@@ -267,8 +267,8 @@ def test_norms_validation(L):
 def test_autotuner_candidates_parse(L):
     """Every schedule the autotuner would time names compiled variants at
     heights the library accepts, including the held (two workgroups per CU)
-    strided tiles; the held strided variants it knows are exactly the
-    compiled ones."""
+    strided tiles; the held and wide strided variants it knows are exactly
+    the compiled ones."""
     import paper_1607_01039_amd as F
     from paper_1607_01039_amd import autotune as A
     codes = {"int32": 0, "int64": 1, "float32": 2}
@@ -276,6 +276,8 @@ def test_autotuner_candidates_parse(L):
         names = set(F.list_variants(dt))
         held = {v for v in names if v.startswith("S") and v.rstrip("n").endswith("p")}
         assert {v for v in A.HELD.get(dt, {}).values()} | {v + "n" for v in A.HELD.get(dt, {}).values()} == held
+        wide = {v for v in names if v.rstrip("n").endswith("w")}
+        assert {v for v in A.WIDE.get(dt, {}).values()} | {v + "n" for v in A.WIDE.get(dt, {}).values()} == wide
         for n in (20, 24, 28, 30):
             cands = A.candidates(dt, n)
             assert cands

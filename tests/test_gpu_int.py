@@ -79,7 +79,8 @@ def _variant_cases(dtype):
     for v in F.list_variants(dtype):
         base = v[:-1] if v.endswith("n") else v  # "n": twin with non-temporal loads and stores
         held = base.endswith("p")  # "p": held in registers, two workgroups per CU
-        core = base[:-1] if held else base
+        wide = base.endswith("w")  # "w": the same tile in twice the threads
+        core = base[:-1] if held or wide else base
         if core.startswith("C"):
             tb = int(core[1:])
             if core == "C16" or held:  # only as a first pass over all its bits
