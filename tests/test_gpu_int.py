@@ -207,6 +207,40 @@ def test_fused_threshold_register_strided(F, O, variant):
     assert s in set(gi.tolist())
 
 
+def _wide_int64():
+    import paper_1607_01039_amd as F
+    try:
+        names = F.list_variants("int64")
+    except Exception:  # library not built: the test itself will fail loudly
+        return ["unbuilt"]
+    return [v for v in names if v.rstrip("n").endswith("w")]
+
+
+@pytest.mark.parametrize("variant", _wide_int64())
+def test_fused_threshold_wide_int64(F, O, variant):
+    """The threshold fused into an 8-byte strided tile held by 1024 threads
+    as the last pass: every entry, the hit set and the hit values against the
+    oracle."""
+    core = variant.rstrip("n")[:-1]
+    tb, cb = (int(x) for x in core[1:].split("c"))
+    R = tb - cb
+    n = 12 + R
+    x, s, err = synth.planted(n, 90 + n, 0.4, dtype=np.int64)
+    T = 4 << (n // 2)
+    F.set_schedule("int64", n, f"C12,{variant}:{R}")
+    try:
+        y, hits = _run_int(F, x, threshold=T, cap=1 << n)
+    finally:
+        F.set_schedule("int64", n, None)
+    ref = O.wht_fig1(x)
+    assert np.array_equal(y, ref)
+    ridx, rval, rcnt = O.threshold(ref, T)
+    assert rcnt > 1 and hits.count == rcnt
+    gi, gv = hits.sorted()
+    assert np.array_equal(gi, ridx.astype(np.int64)) and np.array_equal(gv, rval)
+    assert s in set(gi.tolist())
+
+
 @pytest.mark.parametrize("n", [12, 20, 30])
 def test_reused_hit_buffers(F, O, n):
     """The library clears the hit count itself (inside the first of several
